@@ -1,0 +1,142 @@
+"""Serial CPU oracle for truss decomposition (ctypes wrapper over truss_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark use it; the GPU library never imports, links or calls it.
+
+Functions follow Wang & Cheng, "Truss Decomposition in Massive Networks":
+  validate_edges / validate_csr  -- Section 2 (simple undirected graphs)
+  support_def                    -- Definition 1 via Algorithm 1, Steps 2-3
+  support_fwd                    -- Definition 1 via the triangle counting that
+                                    Algorithm 2, Step 2 cites (Section 3.2)
+  truss                          -- Definition 2 / truss number via Algorithm 2
+  csr_to_edges                   -- canonical upper-CSR edge order
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "truss_oracle.c")
+_LIB = os.path.join(_HERE, "_truss_oracle.so")
+
+# error-code magnitudes (negative on return)
+INVAL, TOOBIG, ROWPTR, RANGE, SELFLOOP, UNSORTED, DUP, ASYM, NOMEM = range(1, 10)
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile truss_oracle.c with gcc -O3 into _truss_oracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v2", "-fPIC", "-shared",
+                               "-std=c11", "-Wall", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        c_i64p = ctypes.POINTER(ctypes.c_int64)
+        c_i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_validate_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p]
+        lib.oracle_validate_csr.argtypes = [ctypes.c_int32, ctypes.c_int64, i64p, i32p]
+        lib.oracle_csr_to_edges.argtypes = [ctypes.c_int32, ctypes.c_int64, i64p, i32p, i32p, i32p]
+        for f in (lib.oracle_support_def, lib.oracle_support_fwd):
+            f.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i64p]
+        lib.oracle_truss.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i32p]
+        for f in (lib.oracle_validate_edges, lib.oracle_validate_csr, lib.oracle_csr_to_edges,
+                  lib.oracle_support_def, lib.oracle_support_fwd, lib.oracle_truss):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__("oracle error code %d" % code)
+        self.code = code
+
+
+def _edges(src, dst):
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    if src.shape != dst.shape or src.ndim != 1:
+        raise ValueError("src/dst must be 1-D arrays of equal length")
+    return src, dst
+
+
+def validate_edges(n: int, src, dst) -> int:
+    src, dst = _edges(src, dst)
+    return _load().oracle_validate_edges(n, src.size, src, dst)
+
+
+def validate_csr(n: int, m: int, row_ptr, col) -> int:
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    if row_ptr.size != n + 1:
+        return -INVAL
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.int32)
+    return _load().oracle_validate_csr(n, m, row_ptr, col)
+
+
+def csr_to_edges(n: int, m: int, row_ptr, col):
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    src = np.empty(max(m, 1), dtype=np.int32)
+    dst = np.empty(max(m, 1), dtype=np.int32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.int32)
+    rc = _load().oracle_csr_to_edges(n, m, row_ptr, col, src, dst)
+    if rc:
+        raise OracleError(rc)
+    return src[:m], dst[:m]
+
+
+def _support(fn, n, src, dst):
+    src, dst = _edges(src, dst)
+    rc = _load().oracle_validate_edges(n, src.size, src, dst)
+    if rc:
+        raise OracleError(rc)
+    sup = np.zeros(max(src.size, 1), dtype=np.int32)
+    tri = ctypes.c_int64(0)
+    if src.size:
+        rc = fn(n, src.size, src, dst, sup, ctypes.byref(tri))
+        if rc:
+            raise OracleError(rc)
+    return sup[: src.size], int(tri.value)
+
+
+def support_def(n: int, src, dst):
+    """(sup[m], triangle count) by full-adjacency merge per edge."""
+    return _support(_load().oracle_support_def, n, src, dst)
+
+
+def support_fwd(n: int, src, dst):
+    """(sup[m], triangle count) by degree-oriented forward listing."""
+    return _support(_load().oracle_support_fwd, n, src, dst)
+
+
+def truss(n: int, src, dst):
+    """(phi[m], kmax): truss number of every input edge by Algorithm 2."""
+    src, dst = _edges(src, dst)
+    rc = _load().oracle_validate_edges(n, src.size, src, dst)
+    if rc:
+        raise OracleError(rc)
+    phi = np.zeros(max(src.size, 1), dtype=np.int32)
+    kmax = ctypes.c_int32(0)
+    if src.size:
+        rc = _load().oracle_truss(n, src.size, src, dst, phi, ctypes.byref(kmax))
+        if rc:
+            raise OracleError(rc)
+    return phi[: src.size], int(kmax.value)

@@ -1,0 +1,47 @@
+"""Readers for the text fixtures under tests/golden/."""
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _vid(c):
+    return ord(c) - ord("a")
+
+
+def fig2():
+    """(n, src, dst, phi) of the Example 2 graph, edges in file order."""
+    src, dst, phi = [], [], []
+    with open(os.path.join(GOLDEN, "fig2_example2.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            a, b, k = line.split()
+            src.append(_vid(a))
+            dst.append(_vid(b))
+            phi.append(int(k))
+    return 12, np.array(src, np.int32), np.array(dst, np.int32), np.array(phi, np.int32)
+
+
+def example4():
+    """List of (quantity, (u, v), vertex-or-None, value)."""
+    out = []
+    with open(os.path.join(GOLDEN, "example4_bounds.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            u, v = parts[1].split("-")
+            vert = _vid(parts[2]) if len(parts) == 4 else None
+            out.append((parts[0], (_vid(u), _vid(v)), vert, int(parts[-1])))
+    return out
+
+
+def edge_index(src, dst, u, v):
+    for i in range(len(src)):
+        if {int(src[i]), int(dst[i])} == {u, v}:
+            return i
+    raise KeyError((u, v))
