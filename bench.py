@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark: truss-decomposed edges/s on one MI355X.
+
+A step is one truss_decompose call on the resident input graph: validation,
+CSR build, support counting, peeling, output.  Inputs are generated on the host
+from a seed and copied to HBM before the timed region; the timed region covers
+exactly K steps bracketed by device synchronisation.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(measured with HIP events on the library's stream) and the CPU oracle timed on a
+bounded sample of the same generator family.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "rmat20": "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, deduplicated, int32 CSR",
+    "er2000": "Erdos-Renyi G(n=2000, p=0.01), int32 edge list",
+    "chunglu4m": "Chung-Lu n=4M, exponent 2.1, mean degree 30, cap 200k, 64 planted cliques U{50..500}, int32 CSR",
+    "rmat24": "R-MAT scale 24, edge factor 16, same (a,b,c,d), int32 ids / int64 offsets CSR",
+}
+
+
+def make_graph(name: str, seed: int):
+    import graphgen
+    if name == "rmat20":
+        return graphgen.rmat20(seed), "csr"
+    if name == "er2000":
+        return graphgen.er_small(seed), "edges"
+    if name == "chunglu4m":
+        return graphgen.chung_lu4m(seed), "csr"
+    if name == "rmat24":
+        return graphgen.rmat24(seed), "csr"
+    raise SystemExit("unknown workload " + name)
+
+
+def host_work_model(n, row_ptr, col):
+    """Per-unit counts of the algorithmic byte model: oriented (b, c) pairs the
+    support kernels examine, and the oriented edge count."""
+    deg = np.diff(row_ptr)
+    rows = np.repeat(np.arange(n, dtype=np.int64), deg)
+    c = col.astype(np.int64)
+    before = (deg[rows] < deg[c]) | ((deg[rows] == deg[c]) & (rows < c))
+    dplus = np.bincount(rows[before], minlength=n).astype(np.int64)
+    pairs = int(dplus[c[before]].sum())  # sum over a->b of d+(b)
+    return {"support_pairs": pairs, "oriented_edges": int(before.sum()), "max_outdeg": int(dplus.max(initial=0))}
+
+
+def cpu_baseline(sample_scale: int, seed: int):
+    import graphgen
+    import oracle
+    n, s, d = graphgen.rmat(sample_scale, 16, seed)
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.truss(n, s, d)
+    t = time.perf_counter() - t0
+    return {"value": s.size / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "serial C oracle (support + Algorithm 2 bin-sort peeling), one thread, on R-MAT scale %d "
+                      "edge factor 16 (same generator, m=%d) in %.1f s; full-size oracle runs take minutes"
+                      % (sample_scale, s.size, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--scheduler", default="heuristic", choices=["plain", "heuristic", "learned"])
+    ap.add_argument("--cpu-sample-scale", type=int, default=17)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1205_6693_amd as T
+    T.load_library()
+    torch.cuda.set_device(0)
+
+    print("generating %s seed %d" % (args.workload, args.seed), file=sys.stderr, flush=True)
+    (n, s, d), fmt = make_graph(args.workload, args.seed)
+    import graphgen
+    m = s.size
+    model = None
+    if fmt == "csr":
+        row_ptr, col = graphgen.to_csr(n, s, d)
+        g = T.Graph.from_csr(n, torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda())
+        model = host_work_model(n, row_ptr, col)
+    else:
+        s2, d2 = graphgen.shuffle(s, d, 12345)
+        g = T.Graph.from_edges(n, torch.from_numpy(s2).cuda(), torch.from_numpy(d2).cuda())
+        row_ptr, col = graphgen.to_csr(n, s, d)
+        model = host_work_model(n, row_ptr, col)
+    sched = {"plain": T.SCHED_PLAIN, "heuristic": T.SCHED_HEURISTIC, "learned": T.SCHED_LEARNED}[args.scheduler]
+    opts = T.make_options(scheduler=sched)
+    ws = T.workspace(g, opts)
+    out = torch.empty(m, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    print("n=%d m=%d workspace=%.2f GB" % (n, m, ws.numel() / 1e9), file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        _, st = T.truss_decompose(g, opts, out=out, ws=ws)
+        print("warmup %d: %.2f ms (build %.2f support %.2f peel %.2f) kmax %d subrounds %d"
+              % (i, st["ms_total"], st["ms_build"], st["ms_support"], st["ms_peel"], st["kmax"],
+                 st["subrounds"]), file=sys.stderr, flush=True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, st = T.truss_decompose(g, opts, out=out, ws=ws)
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    print("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+
+    def avg(key):
+        return float(np.mean([x[key] for x in stats]))
+
+    ms_sup, ms_peel, ms_build = avg("ms_support"), avg("ms_peel"), avg("ms_build")
+    st = stats[-1]
+    # algorithmic bytes (per-unit figures are documented in the design doc)
+    sup_bytes = 4 * model["support_pairs"] + 24 * model["oriented_edges"] + 8 * st["triangles"]
+    peel_bytes = 16 * st["peel_work"] + 44 * m
+    kernels = {
+        "support": {"bytes": sup_bytes, "ms": ms_sup},
+        "peel": {"bytes": peel_bytes, "ms": ms_peel},
+    }
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    achieved = kernels[dom]["bytes"] / (kernels[dom]["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom}
+    result = {
+        "metric": "truss-decomposed edges/s", "value": m / (ms_per_step * 1e-3), "unit": "edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "seed": args.seed,
+                   "n": n, "m": m, "scheduler": args.scheduler},
+        "phases_ms": {"build": ms_build, "support": ms_sup, "peel": ms_peel},
+        "kmax": st["kmax"], "levels": st["levels"], "subrounds": st["subrounds"],
+        "triangles": st["triangles"], "peel_work": st["peel_work"],
+        "roofline": roofline,
+        "roofline_all": {k: {"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2), "ms": round(v["ms"], 3),
+                             "bytes": v["bytes"]} for k, v in kernels.items()},
+    }
+    if not args.no_cpu_baseline:
+        print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale, args.seed)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

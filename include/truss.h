@@ -1,0 +1,168 @@
+/*
+ * truss.h — C ABI of the MI355X truss-decomposition library (libtruss.so).
+ *
+ * Problem (Wang & Cheng, "Truss Decomposition in Massive Networks", PVLDB 2012):
+ *   the input is an undirected, unweighted simple graph G = (V, E) (Section 2);
+ *   sup(e) is the number of triangles of G that contain e (Definition 1);
+ *   the k-truss T_k is the largest subgraph in which every edge lies in at least
+ *   k-2 triangles of T_k (Definition 2); the truss number phi(e) is the largest k
+ *   with e in T_k, and the k-class Phi_k is the set of edges with phi(e) = k
+ *   (Definition 3).  Truss decomposition computes every k-truss, equivalently
+ *   phi(e) for every edge, since T_k is the union of the classes Phi_j, j >= k
+ *   (the problem statement of Section 2).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers marked (device) are HIP device pointers; (host) are host
+ *     pointers.  The caller owns every buffer; the library never frees or
+ *     keeps caller memory and holds no state between calls.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All device work is ordered on it, and every call returns only after the
+ *     stream has synchronised, so the returned status is final.
+ *   - Vertex ids, supports, truss numbers and edge ids are int32; offsets,
+ *     edge counts and triangle counts are int64.  m must not exceed INT32_MAX.
+ *   - Duplicated edges and self-loops are rejected, not repaired.
+ *   - Return value: TRUSS_OK (0) or a negative TRUSS_E_* code.  When the input
+ *     violates several rules, the code of smallest magnitude among the
+ *     TRUSS_E_ROWPTR .. TRUSS_E_ASYM group is reported.  Output contents are
+ *     unspecified after an error.  truss_last_error() gives a message for the
+ *     calling thread's last failure.
+ *
+ * Output indexing
+ *   - TRUSS_FMT_EDGES: out[i] belongs to input pair (src[i], dst[i]).
+ *   - TRUSS_FMT_CSR:   out[i] belongs to the i-th edge in canonical upper-CSR
+ *     order: vertices u ascending, and within row u the neighbours v > u in
+ *     row order.
+ */
+#ifndef TRUSS_H
+#define TRUSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRUSS_VERSION 10000
+
+/* ---- status codes ------------------------------------------------------- */
+#define TRUSS_OK 0
+#define TRUSS_E_INVAL (-1)      /* null pointer, negative size, bad option     */
+#define TRUSS_E_TOOBIG (-2)     /* m > INT32_MAX                                */
+#define TRUSS_E_ROWPTR (-3)     /* CSR row_ptr[0] != 0, decreasing, or != 2m    */
+#define TRUSS_E_RANGE (-4)      /* vertex id outside [0, n)                     */
+#define TRUSS_E_SELFLOOP (-5)   /* edge (v, v)                                  */
+#define TRUSS_E_UNSORTED (-6)   /* CSR row not ascending                        */
+#define TRUSS_E_DUP (-7)        /* edge listed twice (either orientation)       */
+#define TRUSS_E_ASYM (-8)       /* CSR has (u,v) without (v,u)                  */
+#define TRUSS_E_NOMEM (-9)      /* device allocation failed                     */
+#define TRUSS_E_WORKSPACE (-10) /* workspace missing or smaller than required   */
+#define TRUSS_E_DEVICE (-11)    /* HIP runtime error                            */
+#define TRUSS_E_INTERNAL (-12)  /* internal limit hit (e.g. sub-round cap)      */
+
+/* ---- graph description -------------------------------------------------- */
+#define TRUSS_FMT_EDGES 0 /* src[m], dst[m]: each undirected edge once, any orientation */
+#define TRUSS_FMT_CSR 1   /* row_ptr[n+1], col[2m]: symmetric, rows strictly ascending  */
+
+typedef struct truss_graph {
+  int32_t n;              /* number of vertices (ids 0..n-1)                  */
+  int32_t fmt;            /* TRUSS_FMT_EDGES or TRUSS_FMT_CSR                 */
+  int64_t m;              /* number of undirected edges                       */
+  const int32_t *src;     /* (device) EDGES: m endpoints                      */
+  const int32_t *dst;     /* (device) EDGES: m endpoints                      */
+  const int64_t *row_ptr; /* (device) CSR: n+1 offsets into col               */
+  const int32_t *col;     /* (device) CSR: 2m neighbour ids                   */
+} truss_graph;
+
+/* ---- options ------------------------------------------------------------ */
+/* Intersection strategy for support counting (Definition 1 by triangle
+ * listing over the (degree, id) orientation; any exact method gives the same
+ * sup, the choice only changes speed). */
+#define TRUSS_SUP_AUTO 0    /* per vertex bin: LDS hash, global binary search   */
+#define TRUSS_SUP_HASH 1    /* N+(u) staged in an LDS hash table                */
+#define TRUSS_SUP_BSEARCH 2 /* binary search of N+(u) in global memory          */
+#define TRUSS_SUP_MERGE 3   /* one wavefront merges N+(u) and N+(v) per edge    */
+
+/* Frontier extraction for peeling. */
+#define TRUSS_PEEL_AUTO 0   /* scheduler decides per level                      */
+#define TRUSS_PEEL_SPARSE 1 /* worklist: enqueue an edge when its support drops to k-2 */
+#define TRUSS_PEEL_DENSE 2  /* re-scan every live edge after each sub-round      */
+
+/* Scheduler used for TRUSS_SUP_AUTO / TRUSS_PEEL_AUTO decisions. */
+#define TRUSS_SCHED_PLAIN 0     /* fixed: bsearch support, dense sweep peeling  */
+#define TRUSS_SCHED_HEURISTIC 1 /* fixed thresholds                             */
+#define TRUSS_SCHED_LEARNED 2   /* MLP over per-level features (model below)    */
+
+typedef struct truss_options {
+  int32_t version;          /* must be TRUSS_VERSION                           */
+  int32_t support_strategy; /* TRUSS_SUP_*                                      */
+  int32_t peel_mode;        /* TRUSS_PEEL_*                                     */
+  int32_t scheduler;        /* TRUSS_SCHED_*                                    */
+  const float *model;       /* (device) learned-scheduler weights, or NULL     */
+  int64_t max_subrounds;    /* > 0: fail with TRUSS_E_INTERNAL past this many  */
+  int32_t grid_blocks;      /* > 0: persistent-kernel workgroups (tuning)      */
+  int32_t reserved[7];
+} truss_options;
+
+/* Filled when a stats pointer is passed (host). */
+typedef struct truss_stats {
+  int64_t n, m;
+  int64_t triangles;  /* |triangles of G|                                    */
+  int32_t kmax;       /* largest truss number (0 when m = 0)                 */
+  int32_t levels;     /* non-empty k-classes visited                         */
+  int64_t subrounds;  /* frontier rounds over all levels                     */
+  int64_t peel_work;  /* adjacency entries scanned while peeling             */
+  double ms_build;    /* validation + CSR build + orientation                */
+  double ms_support;  /* support counting                                    */
+  double ms_peel;     /* peeling                                             */
+  double ms_total;
+  int32_t sched_fallback; /* 1 if the learned model was absent or invalid    */
+  int32_t reserved[7];
+} truss_stats;
+
+/* Fills *opts with defaults: AUTO strategies, heuristic scheduler. */
+void truss_default_options(truss_options *opts);
+
+/* Bytes of device workspace that truss_support / truss_decompose need for a
+ * graph of this shape (only n, m and fmt are read).  bytes: (host). */
+int truss_workspace_size(const truss_graph *g, const truss_options *opts, size_t *bytes);
+
+/* Support of every edge (Definition 1).
+ *   sup_out   (device) int32[m], indexed as in "Output indexing" above.
+ *   triangles (host, nullable) receives |triangles of G| = sum(sup) / 3.
+ *   ws, ws_bytes (device) workspace of at least truss_workspace_size bytes. */
+int truss_support(const truss_graph *g, int32_t *sup_out, int64_t *triangles,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* Truss number of every edge (Definition 2; the k-classes of Definition 3).
+ *   truss_out (device) int32[m], values in [2, k_max], indexed as above.
+ *   opts (host, nullable) options; NULL = truss_default_options.
+ *   stats (host, nullable) filled on success. */
+int truss_decompose(const truss_graph *g, int32_t *truss_out, const truss_options *opts,
+                    truss_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
+/* Truss decomposition of many independent graphs at once.
+ *   num_graphs  G >= 0.
+ *   vtx_off     (host) int64[G+1]: graph g has vertices 0..vtx_off[g+1]-vtx_off[g]-1.
+ *   edge_off    (host) int64[G+1]: graph g owns packed edges edge_off[g]..edge_off[g+1]-1.
+ *   src, dst    (device) int32[edge_off[G]]: graph-local endpoint ids.
+ *   truss_out   (device) int32[edge_off[G]]: truss number of each packed edge.
+ * Triangles never cross graphs, so the result equals decomposing each graph
+ * alone.  Each graph is validated as an edge list; the first failing graph's
+ * code is returned. */
+int truss_batch_workspace_size(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
+                               const truss_options *opts, size_t *bytes);
+int truss_batch(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
+                const int32_t *src, const int32_t *dst, int32_t *truss_out,
+                const truss_options *opts, truss_stats *stats, void *ws, size_t ws_bytes,
+                void *stream);
+
+const char *truss_strerror(int code);
+const char *truss_last_error(void);
+int truss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRUSS_H */

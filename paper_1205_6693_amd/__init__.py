@@ -1,0 +1,240 @@
+"""Python binding of libtruss.so (truss decomposition on MI355X).
+
+Argument marshalling only: every step of support counting and peeling runs in
+the library's HIP kernels.  PyTorch supplies device memory and the stream.
+
+Entry points mirror the C ABI in include/truss.h:
+    truss_support(graph)              -> (sup int32[m] cuda tensor, triangles)
+    truss_decompose(graph, ...)       -> (truss int32[m] cuda tensor, stats dict)
+    truss_batch(vtx_off, edge_off, src, dst, ...) -> (truss int32[M], stats dict)
+    truss_workspace_size(graph)       -> bytes
+Graphs are built with Graph.from_edges(n, src, dst) or
+Graph.from_csr(n, row_ptr, col) from int32/int64 CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtruss.so")
+
+TRUSS_VERSION = 10000
+OK = 0
+E_INVAL, E_TOOBIG, E_ROWPTR, E_RANGE, E_SELFLOOP, E_UNSORTED, E_DUP, E_ASYM, E_NOMEM, E_WORKSPACE, \
+    E_DEVICE, E_INTERNAL = range(-1, -13, -1)
+FMT_EDGES, FMT_CSR = 0, 1
+SUP_AUTO, SUP_HASH, SUP_BSEARCH, SUP_MERGE = 0, 1, 2, 3
+PEEL_AUTO, PEEL_SPARSE, PEEL_DENSE = 0, 1, 2
+SCHED_PLAIN, SCHED_HEURISTIC, SCHED_LEARNED = 0, 1, 2
+
+
+class TrussError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("truss error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("fmt", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("support_strategy", ctypes.c_int32),
+                ("peel_mode", ctypes.c_int32), ("scheduler", ctypes.c_int32),
+                ("model", ctypes.c_void_p), ("max_subrounds", ctypes.c_int64),
+                ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("triangles", ctypes.c_int64),
+                ("kmax", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("subrounds", ctypes.c_int64), ("peel_work", ctypes.c_int64),
+                ("ms_build", ctypes.c_double), ("ms_support", ctypes.c_double),
+                ("ms_peel", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("sched_fallback", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def load_library():
+    """Load libtruss.so; raises if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtruss.so not built: run paper_1205_6693_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    gp = ctypes.POINTER(_Graph)
+    op = ctypes.POINTER(Options)
+    sp = ctypes.POINTER(Stats)
+    lib.truss_default_options.argtypes = [op]
+    lib.truss_default_options.restype = None
+    lib.truss_workspace_size.argtypes = [gp, op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.truss_support.argtypes = [gp, vp, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
+    lib.truss_decompose.argtypes = [gp, vp, op, sp, vp, ctypes.c_size_t, vp]
+    lib.truss_batch_workspace_size.argtypes = [i32, vp, vp, op, ctypes.POINTER(ctypes.c_size_t)]
+    lib.truss_batch.argtypes = [i32, vp, vp, vp, vp, vp, op, sp, vp, ctypes.c_size_t, vp]
+    for f in ("truss_workspace_size", "truss_support", "truss_decompose",
+              "truss_batch_workspace_size", "truss_batch", "truss_version"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.truss_strerror.argtypes = [ctypes.c_int]
+    lib.truss_strerror.restype = ctypes.c_char_p
+    lib.truss_last_error.restype = ctypes.c_char_p
+    lib.truss_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load_library()
+        raise TrussError(rc, (lib.truss_last_error() or lib.truss_strerror(rc)).decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Graph:
+    """A simple undirected graph resident in device memory."""
+
+    def __init__(self, n, m, fmt, src=None, dst=None, row_ptr=None, col=None):
+        self.n, self.m, self.fmt = int(n), int(m), fmt
+        self.src, self.dst, self.row_ptr, self.col = src, dst, row_ptr, col
+
+    @classmethod
+    def from_edges(cls, n, src, dst):
+        torch = _torch()
+        src = src.to(torch.int32).contiguous()
+        dst = dst.to(torch.int32).contiguous()
+        if src.shape != dst.shape or src.dim() != 1:
+            raise ValueError("src and dst must be 1-D and of equal length")
+        return cls(n, src.numel(), FMT_EDGES, src=src, dst=dst)
+
+    @classmethod
+    def from_csr(cls, n, row_ptr, col):
+        torch = _torch()
+        row_ptr = row_ptr.to(torch.int64).contiguous()
+        col = col.to(torch.int32).contiguous()
+        if col.numel() % 2:
+            raise ValueError("a symmetric CSR has an even number of entries")
+        return cls(n, col.numel() // 2, FMT_CSR, row_ptr=row_ptr, col=col)
+
+    def _c(self):
+        g = _Graph()
+        g.n, g.fmt, g.m = self.n, self.fmt, self.m
+        if self.fmt == FMT_EDGES:
+            g.src, g.dst = _ptr(self.src).value, _ptr(self.dst).value
+        else:
+            g.row_ptr, g.col = _ptr(self.row_ptr).value, _ptr(self.col).value
+        return g
+
+    @property
+    def device(self):
+        t = self.src if self.fmt == FMT_EDGES else self.row_ptr
+        return t.device
+
+
+def make_options(support_strategy=SUP_AUTO, peel_mode=PEEL_AUTO, scheduler=SCHED_HEURISTIC,
+                 model=None, max_subrounds=0, grid_blocks=0):
+    o = Options()
+    load_library().truss_default_options(ctypes.byref(o))
+    o.support_strategy, o.peel_mode, o.scheduler = support_strategy, peel_mode, scheduler
+    o.model = _ptr(model).value if model is not None else None
+    o.max_subrounds, o.grid_blocks = max_subrounds, grid_blocks
+    return o
+
+
+def truss_workspace_size(graph: Graph, opts: Options | None = None) -> int:
+    lib = load_library()
+    b = ctypes.c_size_t(0)
+    g = graph._c()
+    _check(lib.truss_workspace_size(ctypes.byref(g), ctypes.byref(opts) if opts else None, ctypes.byref(b)))
+    return b.value
+
+
+def workspace(graph: Graph, opts: Options | None = None):
+    torch = _torch()
+    return torch.empty(truss_workspace_size(graph, opts), dtype=torch.uint8, device=graph.device)
+
+
+def truss_support(graph: Graph, out=None, ws=None, stream=None):
+    """sup(e) of every edge (Definition 1) and the triangle count."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    if ws is None:
+        ws = workspace(graph)
+    tri = ctypes.c_int64(0)
+    g = graph._c()
+    _check(lib.truss_support(ctypes.byref(g), _ptr(out), ctypes.byref(tri), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    return out, tri.value
+
+
+def truss_decompose(graph: Graph, opts: Options | None = None, out=None, ws=None, stream=None):
+    """Truss number of every edge (Definition 2) and run statistics."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    if ws is None:
+        ws = workspace(graph, opts)
+    st = Stats()
+    g = graph._c()
+    _check(lib.truss_decompose(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
+                               ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream)))
+    return out, st.to_dict()
+
+
+def truss_batch_workspace_size(vtx_off, edge_off, opts: Options | None = None) -> int:
+    import numpy as np
+    lib = load_library()
+    vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    eo = np.ascontiguousarray(edge_off, dtype=np.int64)
+    b = ctypes.c_size_t(0)
+    _check(lib.truss_batch_workspace_size(len(vo) - 1, vo.ctypes.data, eo.ctypes.data,
+                                          ctypes.byref(opts) if opts else None, ctypes.byref(b)))
+    return b.value
+
+
+def truss_batch(vtx_off, edge_off, src, dst, opts: Options | None = None, out=None, ws=None, stream=None):
+    """Truss numbers of many independent graphs packed together (graph-local ids)."""
+    import numpy as np
+    torch = _torch()
+    lib = load_library()
+    vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    eo = np.ascontiguousarray(edge_off, dtype=np.int64)
+    src = src.to(torch.int32).contiguous()
+    dst = dst.to(torch.int32).contiguous()
+    if out is None:
+        out = torch.empty(src.numel(), dtype=torch.int32, device=src.device)
+    if ws is None:
+        ws = torch.empty(max(1, truss_batch_workspace_size(vo, eo, opts)), dtype=torch.uint8,
+                         device=src.device)
+    st = Stats()
+    _check(lib.truss_batch(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
+                           ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
+                           _stream(stream)))
+    return out, st.to_dict()

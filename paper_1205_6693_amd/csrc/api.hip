@@ -1,0 +1,361 @@
+// C ABI of libtruss.so (declarations and contracts in include/truss.h).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace truss {
+
+namespace {
+thread_local char g_last_error[512] = "";
+
+constexpr int kT = 256;
+
+__global__ void k_scatter_out(const int32_t* __restrict__ val, const int32_t* __restrict__ perm, int64_t m,
+                              int32_t* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < m) out[perm ? perm[e] : e] = val[e];
+}
+
+__global__ void k_scatter_sup(const int2* __restrict__ sr, const int32_t* __restrict__ perm, int64_t m,
+                              int32_t* __restrict__ out, unsigned long long* total) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned long long x = 0;
+  if (e < m) {
+    const int s = sr[e].x;
+    out[perm ? perm[e] : e] = s;
+    x = (unsigned long long)s;
+  }
+  x = wave_sum(x);
+  if (lane_id() == 0 && x) atomicAdd(total, x);
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0; }
+
+__global__ void k_sum_sup(const int2* __restrict__ sr, int64_t m, unsigned long long* total) {
+  unsigned long long x = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+    x += (unsigned long long)sr[e].x;
+  x = wave_sum(x);
+  if (lane_id() == 0 && x) atomicAdd(total, x);
+}
+
+inline unsigned grid_for(int64_t n) {
+  const int64_t b = (n + kT - 1) / kT;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+int check_graph(const truss_graph* g) {
+  if (!g) { set_last_error("graph is NULL"); return TRUSS_E_INVAL; }
+  if (g->n < 0 || g->m < 0) { set_last_error("negative n or m"); return TRUSS_E_INVAL; }
+  if (g->m > 0x7fffffffLL) { set_last_error("m exceeds INT32_MAX"); return TRUSS_E_TOOBIG; }
+  if (g->fmt == TRUSS_FMT_EDGES) {
+    if (g->m > 0 && (!g->src || !g->dst)) { set_last_error("src/dst is NULL"); return TRUSS_E_INVAL; }
+  } else if (g->fmt == TRUSS_FMT_CSR) {
+    if (!g->row_ptr || (g->m > 0 && !g->col)) { set_last_error("row_ptr/col is NULL"); return TRUSS_E_INVAL; }
+  } else {
+    set_last_error("unknown graph format %d", g->fmt);
+    return TRUSS_E_INVAL;
+  }
+  return TRUSS_OK;
+}
+
+int check_opts(const truss_options* o) {
+  if (!o) return TRUSS_OK;
+  if (o->version != TRUSS_VERSION) { set_last_error("options version mismatch"); return TRUSS_E_INVAL; }
+  if (o->support_strategy < TRUSS_SUP_AUTO || o->support_strategy > TRUSS_SUP_MERGE ||
+      o->peel_mode < TRUSS_PEEL_AUTO || o->peel_mode > TRUSS_PEEL_DENSE ||
+      o->scheduler < TRUSS_SCHED_PLAIN || o->scheduler > TRUSS_SCHED_LEARNED) {
+    set_last_error("option out of range");
+    return TRUSS_E_INVAL;
+  }
+  return TRUSS_OK;
+}
+
+// Resolve AUTO choices of the scheduler into concrete strategies.
+void resolve(const truss_options* in, truss_options* out, int* fallback) {
+  truss_default_options(out);
+  if (in) *out = *in;
+  *fallback = 0;
+  int sched = out->scheduler;
+  if (sched == TRUSS_SCHED_LEARNED && out->model == nullptr) {
+    *fallback = 1;
+    sched = TRUSS_SCHED_HEURISTIC;
+  }
+  if (out->support_strategy == TRUSS_SUP_AUTO)
+    out->support_strategy = sched == TRUSS_SCHED_PLAIN ? TRUSS_SUP_BSEARCH : TRUSS_SUP_HASH;
+  if (out->peel_mode == TRUSS_PEEL_AUTO && sched == TRUSS_SCHED_PLAIN) out->peel_mode = TRUSS_PEEL_DENSE;
+  if (out->peel_mode == TRUSS_PEEL_AUTO) out->peel_mode = TRUSS_PEEL_SPARSE;
+}
+
+struct Plan {
+  int* d_err = nullptr;
+  unsigned long long* d_total = nullptr;
+  int2* sr = nullptr;
+  int32_t* truss_canon = nullptr;
+};
+
+// One layout for size queries and runs: header, build, per-edge state, support, peel.
+void layout(const truss_graph* g, Arena& a, Plan& p, DevGraph* dg_for_sizes) {
+  p.d_err = a.take<int>(64);
+  p.d_total = a.take<unsigned long long>(8);
+  build_workspace(g, a);
+  p.sr = a.take<int2>((size_t)g->m + 1);
+  p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
+  DevGraph dg;
+  dg.n = g->n;
+  dg.m = g->m;
+  if (dg_for_sizes) dg = *dg_for_sizes;
+  support_workspace(dg, a);
+  peel_workspace(dg, a);
+}
+
+struct Timer {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool on = false;
+  hipStream_t s;
+  explicit Timer(bool enable, hipStream_t st) : on(enable), s(st) {
+    if (on)
+      for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) on = false;
+  }
+  void mark(int i) {
+    if (on) (void)hipEventRecord(ev[i], s);
+  }
+  double ms(int a, int b) {
+    float t = 0.f;
+    if (!on) return 0.0;
+    if (hipEventSynchronize(ev[b]) != hipSuccess) return 0.0;
+    if (hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
+    return t;
+  }
+  ~Timer() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// Runs build + support, then either scatters sup (want_truss false) or peels.
+int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* triangles,
+               const truss_options* opts_in, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  rc = check_opts(opts_in);
+  if (rc) return rc;
+  if (g->m > 0 && !out) { set_last_error("output is NULL"); return TRUSS_E_INVAL; }
+  truss_options opts;
+  int fallback = 0;
+  resolve(opts_in, &opts, &fallback);
+  Arena need;
+  need.counting = true;
+  Plan dummy;
+  layout(g, need, dummy, nullptr);
+  if (!ws || ws_bytes < need.used) {
+    set_last_error("workspace of %zu bytes given, %zu needed", ws_bytes, need.used);
+    return TRUSS_E_WORKSPACE;
+  }
+  Arena a;
+  a.base = static_cast<char*>(ws);
+  a.cap = ws_bytes;
+  Plan p;
+  p.d_err = a.take<int>(64);
+  p.d_total = a.take<unsigned long long>(8);
+  Timer tm(stats != nullptr, s);
+  tm.mark(0);
+  DevGraph dg;
+  rc = build_graph(g, a, dg, p.d_err, s);
+  if (rc) return rc;
+  tm.mark(1);
+  p.sr = a.take<int2>((size_t)g->m + 1);
+  p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
+  rc = compute_support(dg, opts.support_strategy, p.sr, a, s);
+  if (rc) return rc;
+  tm.mark(2);
+  PeelResult pr;
+  unsigned long long tot = 0;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p.d_total);
+  if (!want_truss) {
+    if (g->m > 0)
+      hipLaunchKernelGGL(k_scatter_sup, dim3(grid_for(g->m)), dim3(kT), 0, s, p.sr, dg.perm, g->m, out, p.d_total);
+    TRUSS_HIP(hipMemcpyAsync(&tot, p.d_total, sizeof(tot), hipMemcpyDeviceToHost, s));
+    TRUSS_HIP(hipStreamSynchronize(s));
+    if (triangles) *triangles = (int64_t)(tot / 3);
+    tm.mark(3);
+  } else {
+    if (stats && g->m > 0) hipLaunchKernelGGL(k_sum_sup, dim3(1024), dim3(kT), 0, s, p.sr, g->m, p.d_total);
+    int32_t* tc = g->fmt == TRUSS_FMT_EDGES ? p.truss_canon : out;
+    rc = peel(dg, &opts, p.sr, tc, a, &pr, s);
+    if (rc) return rc;
+    if (g->fmt == TRUSS_FMT_EDGES && g->m > 0)
+      hipLaunchKernelGGL(k_scatter_out, dim3(grid_for(g->m)), dim3(kT), 0, s, tc, dg.perm, g->m, out);
+    tm.mark(3);
+    TRUSS_HIP(hipGetLastError());
+    if (stats) TRUSS_HIP(hipMemcpyAsync(&tot, p.d_total, sizeof(tot), hipMemcpyDeviceToHost, s));
+    TRUSS_HIP(hipStreamSynchronize(s));
+  }
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->n = g->n;
+    stats->m = g->m;
+    stats->kmax = pr.kmax;
+    stats->levels = pr.levels;
+    stats->subrounds = pr.subrounds;
+    stats->peel_work = pr.work;
+    stats->ms_build = tm.ms(0, 1);
+    stats->ms_support = tm.ms(1, 2);
+    stats->ms_peel = tm.ms(2, 3);
+    stats->ms_total = tm.ms(0, 3);
+    stats->sched_fallback = fallback;
+    stats->triangles = (int64_t)(tot / 3);
+  }
+  return TRUSS_OK;
+}
+
+}  // namespace
+
+void set_last_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+
+int device_grid_blocks(const void* kernel, int block, size_t lds) {
+  int dev = 0, cus = 0, occ = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, lds) != hipSuccess || occ < 1) occ = 1;
+  if (occ > 4) occ = 4;
+  return cus * occ;
+}
+
+}  // namespace truss
+
+using namespace truss;
+
+extern "C" {
+
+void truss_default_options(truss_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->version = TRUSS_VERSION;
+  o->support_strategy = TRUSS_SUP_AUTO;
+  o->peel_mode = TRUSS_PEEL_AUTO;
+  o->scheduler = TRUSS_SCHED_HEURISTIC;
+}
+
+int truss_workspace_size(const truss_graph* g, const truss_options* opts, size_t* bytes) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  rc = check_opts(opts);
+  if (rc) return rc;
+  if (!bytes) { set_last_error("bytes is NULL"); return TRUSS_E_INVAL; }
+  Arena a;
+  a.counting = true;
+  Plan p;
+  layout(g, a, p, nullptr);
+  *bytes = a.used;
+  return TRUSS_OK;
+}
+
+int truss_support(const truss_graph* g, int32_t* sup_out, int64_t* triangles, void* ws, size_t ws_bytes,
+                  void* stream) {
+  if (triangles) *triangles = 0;
+  if (g && g->m > 0 && !sup_out) { set_last_error("sup_out is NULL"); return TRUSS_E_INVAL; }
+  return run_single(g, false, sup_out, triangles, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int truss_decompose(const truss_graph* g, int32_t* truss_out, const truss_options* opts, truss_stats* stats,
+                    void* ws, size_t ws_bytes, void* stream) {
+  if (g && g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
+  return run_single(g, true, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int truss_batch_workspace_size(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
+                               const truss_options* opts, size_t* bytes) {
+  if (num_graphs < 0 || !bytes || (num_graphs > 0 && (!vtx_off || !edge_off))) {
+    set_last_error("bad batch arguments");
+    return TRUSS_E_INVAL;
+  }
+  size_t best = 0;
+  for (int32_t i = 0; i < num_graphs; ++i) {
+    truss_graph g;
+    memset(&g, 0, sizeof(g));
+    g.fmt = TRUSS_FMT_EDGES;
+    g.n = (int32_t)(vtx_off[i + 1] - vtx_off[i]);
+    g.m = edge_off[i + 1] - edge_off[i];
+    g.src = g.dst = reinterpret_cast<const int32_t*>(1);
+    size_t b = 0;
+    int rc = truss_workspace_size(&g, opts, &b);
+    if (rc) return rc;
+    if (b > best) best = b;
+  }
+  *bytes = best;
+  return TRUSS_OK;
+}
+
+int truss_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off, const int32_t* src,
+                const int32_t* dst, int32_t* truss_out, const truss_options* opts, truss_stats* stats, void* ws,
+                size_t ws_bytes, void* stream) {
+  if (num_graphs < 0 || (num_graphs > 0 && (!vtx_off || !edge_off))) {
+    set_last_error("bad batch arguments");
+    return TRUSS_E_INVAL;
+  }
+  if (stats) memset(stats, 0, sizeof(*stats));
+  for (int32_t i = 0; i < num_graphs; ++i) {
+    if (vtx_off[i + 1] < vtx_off[i] || edge_off[i + 1] < edge_off[i] || vtx_off[i + 1] - vtx_off[i] > 0x7fffffffLL) {
+      set_last_error("batch offsets of graph %d are not monotone", i);
+      return TRUSS_E_INVAL;
+    }
+    truss_graph g;
+    memset(&g, 0, sizeof(g));
+    g.fmt = TRUSS_FMT_EDGES;
+    g.n = (int32_t)(vtx_off[i + 1] - vtx_off[i]);
+    g.m = edge_off[i + 1] - edge_off[i];
+    g.src = src + edge_off[i];
+    g.dst = dst + edge_off[i];
+    truss_stats st;
+    int rc = truss_decompose(&g, truss_out + edge_off[i], opts, stats ? &st : nullptr, ws, ws_bytes, stream);
+    if (rc) return rc;
+    if (stats) {
+      stats->n += st.n;
+      stats->m += st.m;
+      if (st.kmax > stats->kmax) stats->kmax = st.kmax;
+      stats->levels += st.levels;
+      stats->subrounds += st.subrounds;
+      stats->peel_work += st.peel_work;
+      stats->ms_build += st.ms_build;
+      stats->ms_support += st.ms_support;
+      stats->ms_peel += st.ms_peel;
+      stats->ms_total += st.ms_total;
+    }
+  }
+  return TRUSS_OK;
+}
+
+const char* truss_strerror(int code) {
+  switch (code) {
+    case TRUSS_OK: return "success";
+    case TRUSS_E_INVAL: return "invalid argument";
+    case TRUSS_E_TOOBIG: return "graph too large (m > INT32_MAX)";
+    case TRUSS_E_ROWPTR: return "invalid CSR row_ptr";
+    case TRUSS_E_RANGE: return "vertex id out of range";
+    case TRUSS_E_SELFLOOP: return "self-loop";
+    case TRUSS_E_UNSORTED: return "CSR row not strictly ascending";
+    case TRUSS_E_DUP: return "duplicate edge";
+    case TRUSS_E_ASYM: return "CSR not symmetric";
+    case TRUSS_E_NOMEM: return "out of device memory";
+    case TRUSS_E_WORKSPACE: return "workspace too small";
+    case TRUSS_E_DEVICE: return "HIP runtime error";
+    case TRUSS_E_INTERNAL: return "internal limit reached";
+    default: return "unknown error";
+  }
+}
+
+const char* truss_last_error(void) { return g_last_error; }
+
+int truss_version(void) { return TRUSS_VERSION; }
+
+}  // extern "C"

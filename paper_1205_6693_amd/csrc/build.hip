@@ -1,0 +1,361 @@
+// Graph build: validation of the simple-graph contract (Section 2), canonical
+// edge ids, the symmetric CSR with edge ids, and the (degree, id) orientation
+// used for triangle listing (the in-memory triangle counting that Algorithm 2,
+// Step 2 relies on; the smaller-degree rule of Step 6 and Theorem 1).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace truss {
+
+namespace {
+
+constexpr int kT = 256;
+
+inline unsigned grid_for(int64_t n, int per_block = kT) {
+  int64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (1LL << 30)) b = 1LL << 30;
+  return (unsigned)b;
+}
+
+inline int bits_for(int64_t n) {
+  int b = 0;
+  while (b < 62 && (1LL << b) < n) ++b;
+  return b;
+}
+
+__device__ __forceinline__ void report(int* err, int code) { atomicMin(err, code); }
+
+__global__ void k_init_err(int* err) { *err = kNoErr; }
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---- edge-list input ----------------------------------------------------------------
+
+__global__ void k_canon(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t m, int32_t n,
+                        int vb, uint64_t* __restrict__ key, int32_t* __restrict__ val, int* err) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int32_t u = src[i], v = dst[i];
+  int code = 0;
+  if (u < 0 || u >= n || v < 0 || v >= n) code = kErrRange;
+  else if (u == v) code = kErrSelfloop;
+  if (code) { report(err, code); u = 0; v = 0; }
+  uint64_t a = (uint64_t)(u < v ? u : v), b = (uint64_t)(u < v ? v : u);
+  key[i] = (a << vb) | b;
+  val[i] = (int32_t)i;
+}
+
+__global__ void k_edges_from_keys(const uint64_t* __restrict__ key, const int32_t* __restrict__ val, int64_t m,
+                                  int vb, int32_t* __restrict__ eu, int32_t* __restrict__ ev,
+                                  int32_t* __restrict__ perm, int32_t* __restrict__ upcnt,
+                                  int32_t* __restrict__ lowcnt, int* err) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  uint64_t k = key[e];
+  if (e > 0 && key[e - 1] == k) report(err, kErrDup);
+  int32_t u = (int32_t)(k >> vb), v = (int32_t)(k & ((1ULL << vb) - 1));
+  eu[e] = u;
+  ev[e] = v;
+  perm[e] = val[e];
+  atomicAdd(&upcnt[u], 1);
+  atomicAdd(&lowcnt[v], 1);
+}
+
+__global__ void k_rowptr_sum(const int64_t* __restrict__ a, const int64_t* __restrict__ b, int32_t n,
+                             int64_t* __restrict__ out) {
+  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v <= n) out[v] = a[v] + b[v];
+}
+
+__device__ __forceinline__ int64_t deg_of(const int64_t* __restrict__ rp, int32_t v) { return rp[v + 1] - rp[v]; }
+
+__global__ void k_sym_upper(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
+                            const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ lowcnt,
+                            const int64_t* __restrict__ uppre, int32_t* __restrict__ col,
+                            int32_t* __restrict__ seid, int32_t* __restrict__ kf) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  int32_t u = eu[e], v = ev[e];
+  int64_t pos = row_ptr[u] + lowcnt[u] + (e - uppre[u]);
+  col[pos] = v;
+  seid[pos] = (int32_t)e;
+  kf[pos] = vertex_before(deg_of(row_ptr, u), u, deg_of(row_ptr, v), v) ? 1 : 0;
+}
+
+__global__ void k_copy_ev(const int32_t* __restrict__ ev, int64_t m, uint32_t* __restrict__ tkey,
+                          int32_t* __restrict__ tval) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  tkey[e] = (uint32_t)ev[e];
+  tval[e] = (int32_t)e;
+}
+
+__global__ void k_sym_lower(const uint32_t* __restrict__ tkey, const int32_t* __restrict__ tval, int64_t m,
+                            const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ lowpre,
+                            const int32_t* __restrict__ eu, int32_t* __restrict__ col,
+                            int32_t* __restrict__ seid, int32_t* __restrict__ kf) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  int32_t e = tval[t];
+  int32_t v = (int32_t)tkey[t];
+  int32_t u = eu[e];
+  int64_t pos = row_ptr[v] + (t - lowpre[v]);
+  col[pos] = u;
+  seid[pos] = e;
+  kf[pos] = vertex_before(deg_of(row_ptr, v), v, deg_of(row_ptr, u), u) ? 1 : 0;
+}
+
+// ---- CSR input -------------------------------------------------------------------------
+
+__global__ void k_rowptr_check(const int64_t* __restrict__ row_ptr, int32_t n, int64_t m2, int* err) {
+  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v > n) return;
+  int64_t r = row_ptr[v];
+  if (v == 0 && r != 0) report(err, kErrRowptr);
+  if (v == n && r != m2) report(err, kErrRowptr);
+  if (v < n && row_ptr[v + 1] < r) report(err, kErrRowptr);
+  if (r < 0 || r > m2) report(err, kErrRowptr);
+}
+
+// one wavefront per row writes the row id of each entry
+__global__ void k_rowid(const int64_t* __restrict__ row_ptr, int32_t n, int32_t* __restrict__ rowid) {
+  const int lane = lane_id();
+  const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t v = wid; v < n; v += nw) {
+    const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+    for (int64_t j = b + lane; j < e; j += kWave) rowid[j] = (int32_t)v;
+  }
+}
+
+__global__ void k_csr_check(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t n,
+                            int64_t m2, const int32_t* __restrict__ rowid, int32_t* __restrict__ uf, int* err) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m2) return;
+  const int32_t v = rowid[j], w = col[j];
+  int code = 0;
+  if (w < 0 || w >= n) code = kErrRange;
+  else if (w == v) code = kErrSelfloop;
+  else if (j + 1 < row_ptr[v + 1]) {
+    const int32_t x = col[j + 1];
+    if (x == w) code = kErrDup;
+    else if (x < w && x >= 0) code = kErrUnsorted;
+  }
+  if (code) report(err, code);
+  uf[j] = (w > v && w < n) ? 1 : 0;
+}
+
+__global__ void k_csr_upper(const int32_t* __restrict__ col, const int32_t* __restrict__ rowid,
+                            const int64_t* __restrict__ upos, int64_t m2, int32_t* __restrict__ colcopy,
+                            int32_t* __restrict__ seid, int32_t* __restrict__ eu, int32_t* __restrict__ ev) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m2) return;
+  const int32_t v = rowid[j], w = col[j];
+  colcopy[j] = w;
+  if (w > v) {
+    const int64_t e = upos[j];
+    seid[j] = (int32_t)e;
+    eu[e] = v;
+    ev[e] = w;
+  }
+}
+
+__global__ void k_csr_lower(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                            const int32_t* __restrict__ rowid, const int64_t* __restrict__ upos, int64_t m2,
+                            int32_t* __restrict__ seid, int32_t* __restrict__ kf, int* err) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m2) return;
+  const int32_t v = rowid[j], w = col[j];
+  if (w < v) {
+    const int64_t lo = row_ptr[w], hi = row_ptr[w + 1];
+    const int64_t p = lower_bound_i32<int64_t>(col, lo, hi, v);
+    if (p >= hi || col[p] != v) report(err, kErrAsym);
+    else seid[j] = (int32_t)upos[p];
+  }
+  kf[j] = vertex_before(deg_of(row_ptr, v), v, deg_of(row_ptr, w), w) ? 1 : 0;
+}
+
+__global__ void k_check_total(const int64_t* __restrict__ upos, int64_t m2, int64_t m, int* err) {
+  if (upos[m2] != m) report(err, kErrAsym);
+}
+
+// ---- orientation ------------------------------------------------------------------------
+
+__global__ void k_orow(const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ opos, int32_t n,
+                       int64_t* __restrict__ orow) {
+  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v <= n) orow[v] = opos[row_ptr[v]];
+}
+
+__global__ void k_ocsr(const int32_t* __restrict__ col, const int32_t* __restrict__ seid,
+                       const int32_t* __restrict__ kf, const int64_t* __restrict__ opos, int64_t m2,
+                       int32_t* __restrict__ ocol, int32_t* __restrict__ oeid) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m2) return;
+  if (kf[j]) {
+    const int64_t p = opos[j];
+    ocol[p] = col[j];
+    oeid[p] = seid[j];
+  }
+}
+
+int read_err(const int* d_err, hipStream_t s) {
+  int h = kNoErr;
+  TRUSS_HIP(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  TRUSS_HIP(hipStreamSynchronize(s));
+  if (h == kNoErr) return TRUSS_OK;
+  switch (h) {
+    case kErrRowptr: set_last_error("CSR row_ptr is not a valid offset array for 2m entries"); break;
+    case kErrRange: set_last_error("vertex id outside [0, n)"); break;
+    case kErrSelfloop: set_last_error("self-loop in input (simple graphs only)"); break;
+    case kErrUnsorted: set_last_error("CSR row not strictly ascending"); break;
+    case kErrDup: set_last_error("edge listed more than once"); break;
+    case kErrAsym: set_last_error("CSR is not symmetric"); break;
+    default: set_last_error("validation failed (%d)", h); break;
+  }
+  return -h;
+}
+
+// buffers of the build, laid out identically for the size query and the run
+struct Layout {
+  // resident
+  int32_t *col, *seid, *eu, *ev, *perm, *ocol, *oeid;
+  int64_t *row_ptr, *orow;
+  // temporaries
+  uint64_t *key, *key_alt;
+  int32_t *val, *val_alt;
+  int32_t *upcnt, *lowcnt;
+  int64_t *uppre, *lowpre;
+  int32_t *rowid, *kf;
+  int64_t *opos;
+  int32_t *rtmp;
+  int64_t *stmp;
+};
+
+void carve(const truss_graph* g, Arena& a, Layout& L) {
+  const int64_t n = g->n, m = g->m, m2 = 2 * m;
+  const bool edges = g->fmt == TRUSS_FMT_EDGES;
+  L.col = a.take<int32_t>(m2 + 1);
+  L.seid = a.take<int32_t>(m2 + 1);
+  L.eu = a.take<int32_t>(m + 1);
+  L.ev = a.take<int32_t>(m + 1);
+  L.ocol = a.take<int32_t>(m + 1);
+  L.oeid = a.take<int32_t>(m + 1);
+  L.orow = a.take<int64_t>(n + 1);
+  L.perm = edges ? a.take<int32_t>(m + 1) : nullptr;
+  L.row_ptr = edges ? a.take<int64_t>(n + 1) : nullptr;
+  // temporaries (could alias peeling state; kept separate for clarity)
+  L.kf = a.take<int32_t>(m2 + 1);
+  L.opos = a.take<int64_t>(m2 + 1);
+  L.stmp = a.take<int64_t>(scan_tmp_elems(m2 + 1) + scan_tmp_elems(n + 1));
+  if (edges) {
+    L.key = a.take<uint64_t>(m + 1);
+    L.key_alt = a.take<uint64_t>(m + 1);
+    L.val = a.take<int32_t>(m + 1);
+    L.val_alt = a.take<int32_t>(m + 1);
+    L.upcnt = a.take<int32_t>(n + 1);
+    L.lowcnt = a.take<int32_t>(n + 1);
+    L.uppre = a.take<int64_t>(n + 1);
+    L.lowpre = a.take<int64_t>(n + 1);
+    L.rtmp = a.take<int32_t>(radix_tmp_elems(m + 1));
+    L.rowid = nullptr;
+  } else {
+    L.rowid = a.take<int32_t>(m2 + 1);
+    L.key = L.key_alt = nullptr;
+    L.val = L.val_alt = nullptr;
+    L.upcnt = L.lowcnt = nullptr;
+    L.uppre = L.lowpre = nullptr;
+    L.rtmp = nullptr;
+  }
+}
+
+}  // namespace
+
+size_t build_workspace(const truss_graph* g, Arena& a) {
+  Layout L;
+  carve(g, a, L);
+  return a.used;
+}
+
+int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStream_t s) {
+  Layout L;
+  carve(g, a, L);
+  if (a.overflow()) return TRUSS_E_WORKSPACE;
+  const int32_t n = g->n;
+  const int64_t m = g->m, m2 = 2 * m;
+  dg.n = n;
+  dg.m = m;
+  hipLaunchKernelGGL(k_init_err, dim3(1), dim3(1), 0, s, d_err);
+
+  if (g->fmt == TRUSS_FMT_EDGES) {
+    const int vb = bits_for(n) > 0 ? bits_for(n) : 1;
+    hipLaunchKernelGGL(k_canon, dim3(grid_for(m)), dim3(kT), 0, s, g->src, g->dst, m, n, vb, L.key, L.val, d_err);
+    int rc = read_err(d_err, s);
+    if (rc) return rc;
+    radix_sort_u64(L.key, L.val, L.key_alt, L.val_alt, m, 2 * vb, L.rtmp, s);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.upcnt, (int64_t)n + 1, 0);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.lowcnt, (int64_t)n + 1, 0);
+    hipLaunchKernelGGL(k_edges_from_keys, dim3(grid_for(m)), dim3(kT), 0, s, L.key, L.val, m, vb, L.eu, L.ev,
+                       L.perm, L.upcnt, L.lowcnt, d_err);
+    rc = read_err(d_err, s);
+    if (rc) return rc;
+    scan_exclusive_i32_to_i64(L.upcnt, L.uppre, n, L.stmp, s);
+    scan_exclusive_i32_to_i64(L.lowcnt, L.lowpre, n, L.stmp, s);
+    hipLaunchKernelGGL(k_rowptr_sum, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.uppre, L.lowpre, n, L.row_ptr);
+    hipLaunchKernelGGL(k_sym_upper, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.row_ptr, L.lowcnt,
+                       L.uppre, L.col, L.seid, L.kf);
+    // lower halves of the rows: stable sort of the canonical order by the larger endpoint
+    uint32_t* tkey = reinterpret_cast<uint32_t*>(L.key);
+    uint32_t* tkey_alt = reinterpret_cast<uint32_t*>(L.key_alt);
+    hipLaunchKernelGGL(k_copy_ev, dim3(grid_for(m)), dim3(kT), 0, s, L.ev, m, tkey, L.val);
+    radix_sort_u32(tkey, L.val, tkey_alt, L.val_alt, m, vb, L.rtmp, s);
+    hipLaunchKernelGGL(k_sym_lower, dim3(grid_for(m)), dim3(kT), 0, s, tkey, L.val, m, L.row_ptr, L.lowpre, L.eu,
+                       L.col, L.seid, L.kf);
+    dg.row_ptr = L.row_ptr;
+    dg.perm = L.perm;
+  } else {
+    hipLaunchKernelGGL(k_rowptr_check, dim3(grid_for((int64_t)n + 1)), dim3(kT), 0, s, g->row_ptr, n, m2, d_err);
+    int rc = read_err(d_err, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_rowid, dim3(grid_for((int64_t)n * kWave > 0 ? (int64_t)n * kWave : 1)), dim3(kT), 0, s,
+                       g->row_ptr, n, L.rowid);
+    int32_t* uf = L.kf;  // upper flags, later reused for orientation flags
+    hipLaunchKernelGGL(k_csr_check, dim3(grid_for(m2)), dim3(kT), 0, s, g->row_ptr, g->col, n, m2, L.rowid, uf,
+                       d_err);
+    rc = read_err(d_err, s);
+    if (rc) return rc;
+    int64_t* upos = L.opos;
+    scan_exclusive_i32_to_i64(uf, upos, m2, L.stmp, s);
+    hipLaunchKernelGGL(k_check_total, dim3(1), dim3(1), 0, s, upos, m2, m, d_err);
+    rc = read_err(d_err, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_csr_upper, dim3(grid_for(m2)), dim3(kT), 0, s, g->col, L.rowid, upos, m2, L.col, L.seid,
+                       L.eu, L.ev);
+    hipLaunchKernelGGL(k_csr_lower, dim3(grid_for(m2)), dim3(kT), 0, s, g->row_ptr, g->col, L.rowid, upos, m2,
+                       L.seid, L.kf, d_err);
+    rc = read_err(d_err, s);
+    if (rc) return rc;
+    dg.row_ptr = g->row_ptr;
+    dg.perm = nullptr;
+  }
+  // oriented CSR: stable compaction of the symmetric rows by the orientation flag
+  scan_exclusive_i32_to_i64(L.kf, L.opos, m2, L.stmp, s);
+  hipLaunchKernelGGL(k_orow, dim3(grid_for((int64_t)n + 1)), dim3(kT), 0, s, dg.row_ptr, L.opos, n, L.orow);
+  hipLaunchKernelGGL(k_ocsr, dim3(grid_for(m2)), dim3(kT), 0, s, L.col, L.seid, L.kf, L.opos, m2, L.ocol, L.oeid);
+  TRUSS_HIP(hipGetLastError());
+  dg.col = L.col;
+  dg.seid = L.seid;
+  dg.eu = L.eu;
+  dg.ev = L.ev;
+  dg.orow = L.orow;
+  dg.ocol = L.ocol;
+  dg.oeid = L.oeid;
+  return TRUSS_OK;
+}
+
+}  // namespace truss

@@ -1,0 +1,103 @@
+// Host-side interfaces between the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/truss.h"
+
+namespace truss {
+
+// error magnitudes reported by device validation (smallest wins)
+enum : int {
+  kErrRowptr = 3, kErrRange = 4, kErrSelfloop = 5, kErrUnsorted = 6, kErrDup = 7, kErrAsym = 8
+};
+constexpr int kNoErr = 0x7fffffff;
+
+// ---- bump allocator over the caller's workspace --------------------------------
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool counting = false;  // size query only
+  template <typename T>
+  T* take(size_t count) {
+    size_t bytes = ((count * sizeof(T)) + 255) & ~size_t(255);
+    size_t at = used;
+    used += bytes;
+    if (counting || base == nullptr) return nullptr;
+    return reinterpret_cast<T*>(base + at);
+  }
+  bool overflow() const { return !counting && used > cap; }
+};
+
+// ---- scan (exclusive prefix sum) ---------------------------------------------
+// out[i] = sum_{j<i} in[i]; out[count] = total (out has count+1 entries).
+// tmp must hold scan_tmp_elems(count) elements of OutT.
+size_t scan_tmp_elems(int64_t count);
+void scan_exclusive_i32_to_i64(const int32_t* in, int64_t* out, int64_t count, int64_t* tmp,
+                               hipStream_t s);
+void scan_exclusive_i32_to_i32(const int32_t* in, int32_t* out, int64_t count, int32_t* tmp,
+                               hipStream_t s);
+
+// ---- radix sort (LSD, 8-bit digits, stable) -------------------------------------
+// Sorts (keys, vals) of length n by the low `bits` bits of the keys.  Uses the
+// *_alt buffers as ping-pong storage; the result ends in keys/vals.
+size_t radix_tmp_elems(int64_t n);
+void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+                    int64_t n, int bits, int32_t* tmp, hipStream_t s);
+void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
+                    int64_t n, int bits, int32_t* tmp, hipStream_t s);
+
+// ---- the resident graph ---------------------------------------------------------
+struct DevGraph {
+  int32_t n = 0;
+  int64_t m = 0;
+  const int64_t* row_ptr = nullptr;  // n+1, symmetric CSR offsets
+  int32_t* col = nullptr;            // 2m neighbours (rows ascending; compacted in place)
+  int32_t* seid = nullptr;           // 2m edge id of each CSR entry
+  int32_t* rlen = nullptr;           // n live row lengths (peeling)
+  int32_t* eu = nullptr;             // m smaller-id endpoint
+  int32_t* ev = nullptr;             // m larger-id endpoint
+  int64_t* orow = nullptr;           // n+1 oriented CSR offsets
+  int32_t* ocol = nullptr;           // m out-neighbours, ascending
+  int32_t* oeid = nullptr;           // m edge ids of oriented entries
+  int32_t* perm = nullptr;           // m canonical edge -> input index (EDGES only)
+  int max_outdeg = 0;
+};
+
+// Build: validation + canonical edge ids + symmetric and oriented CSR.
+// Returns TRUSS_OK or a TRUSS_E_* code; syncs on the stream for the checks.
+struct BuildBufs;
+size_t build_workspace(const truss_graph* g, Arena& a);
+int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStream_t s);
+
+// Support: sr[e].x = sup(e) for every canonical edge (sr must be zeroed inside).
+size_t support_workspace(const DevGraph& dg, Arena& a);
+int compute_support(const DevGraph& dg, int strategy, int2* sr, Arena& a, hipStream_t s);
+
+// Peeling: truss[e] for every canonical edge; sr holds sup on entry.
+struct PeelResult {
+  int32_t kmax = 0, levels = 0;
+  int64_t subrounds = 0, work = 0;
+  int32_t err = 0;
+  int32_t fallback = 0;
+};
+size_t peel_workspace(const DevGraph& dg, Arena& a);
+int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss_canon, Arena& a,
+         PeelResult* res, hipStream_t s);
+
+void set_last_error(const char* fmt, ...);
+int device_grid_blocks(const void* kernel, int block, size_t lds);
+
+}  // namespace truss
+
+#define TRUSS_HIP(call)                                                         \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ::truss::set_last_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                              __FILE__, __LINE__);                              \
+      return TRUSS_E_DEVICE;                                                    \
+    }                                                                           \
+  } while (0)

@@ -1,0 +1,104 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/truss.h declares, and its host-side logic (options, workspace sizing,
+argument checks that fail before any device work) behaves as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "truss.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char|size_t)\s*\*?\s*(truss_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_1205_6693_amd as T
+    return T
+
+
+def test_header_lists_the_boundary():
+    names = declared_functions()
+    for f in ("truss_support", "truss_decompose", "truss_batch", "truss_workspace_size"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(T):
+    lib = T.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_strerror(T):
+    lib = T.load_library()
+    assert lib.truss_version() == T.TRUSS_VERSION
+    for code in range(0, -13, -1):
+        assert lib.truss_strerror(code)
+    assert lib.truss_strerror(-99) == b"unknown error"
+
+
+def test_struct_layouts_match_header(T):
+    # sizes of the ABI structs: graph 48 B, options 64 B, stats 112 B
+    assert ctypes.sizeof(T._Graph) == 48
+    assert ctypes.sizeof(T.Options) == 64
+    assert ctypes.sizeof(T.Stats) == 112
+
+
+def _graph(T, n, m, fmt=0):
+    g = T._Graph()
+    g.n, g.m, g.fmt = n, m, fmt
+    g.src = g.dst = g.row_ptr = g.col = 4096  # never dereferenced by the size query
+    return g
+
+
+def test_workspace_size_is_host_only_and_grows(T):
+    lib = T.load_library()
+    sizes = []
+    for m in (0, 10, 1000, 100000):
+        b = ctypes.c_size_t(0)
+        assert lib.truss_workspace_size(ctypes.byref(_graph(T, 100, m)), None, ctypes.byref(b)) == 0
+        sizes.append(b.value)
+    assert sizes == sorted(sizes) and sizes[-1] > 100000 * 40
+    b = ctypes.c_size_t(0)
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 100, 1000, fmt=1)), None, ctypes.byref(b)) == 0
+
+
+def test_argument_errors_before_device_work(T):
+    lib = T.load_library()
+    b = ctypes.c_size_t(0)
+    assert lib.truss_workspace_size(None, None, ctypes.byref(b)) == T.E_INVAL
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, -1, 5)), None, ctypes.byref(b)) == T.E_INVAL
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 5, 1 << 31)), None, ctypes.byref(b)) == T.E_TOOBIG
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 5, 5, fmt=7)), None, ctypes.byref(b)) == T.E_INVAL
+    o = T.Options()
+    lib.truss_default_options(ctypes.byref(o))
+    assert o.version == T.TRUSS_VERSION
+    o.version = 1
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 5, 5)), ctypes.byref(o), ctypes.byref(b)) == T.E_INVAL
+    o.version = T.TRUSS_VERSION
+    o.peel_mode = 9
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 5, 5)), ctypes.byref(o), ctypes.byref(b)) == T.E_INVAL
+    # decompose with NULL output or too small workspace fails on the host
+    g = _graph(T, 5, 5)
+    assert lib.truss_decompose(ctypes.byref(g), None, None, None, None, 0, None) == T.E_INVAL
+    out = ctypes.c_void_p(4096)
+    assert lib.truss_decompose(ctypes.byref(g), out, None, None, None, 0, None) == T.E_WORKSPACE
+    assert b"workspace" in lib.truss_last_error()
+
+
+def test_batch_workspace_is_max_over_graphs(T):
+    import numpy as np
+    vo = np.array([0, 10, 30, 31], np.int64)
+    eo = np.array([0, 20, 200, 200], np.int64)
+    sz = T.truss_batch_workspace_size(vo, eo)
+    lib = T.load_library()
+    b = ctypes.c_size_t(0)
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 20, 180)), None, ctypes.byref(b)) == 0
+    assert sz == b.value
