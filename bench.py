@@ -125,6 +125,7 @@ def main():
     for i in range(args.steps):
         _, st = T.truss_decompose(g, opts, out=out, ws=ws)
         stats.append(st)
+        print("step %d: %.2f ms" % (i, st["ms_total"]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
@@ -155,7 +156,9 @@ def main():
                    "n": n, "m": m, "scheduler": args.scheduler},
         "phases_ms": {"build": ms_build, "support": ms_sup, "peel": ms_peel},
         "kmax": st["kmax"], "levels": st["levels"], "subrounds": st["subrounds"],
-        "triangles": st["triangles"], "peel_work": st["peel_work"],
+        "triangles": st["triangles"], "peel_work": st["peel_work"], "launches": st["launches"],
+        "heavy_rounds": st["heavy_rounds"], "frontier_hist": st["frontier_hist"],
+        "peel_phase_ms": dict(zip(["sweep", "start", "rounds", "pieces", "dense"], st["ms_phase"][:5])),
         "roofline": roofline,
         "roofline_all": {k: {"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2), "ms": round(v["ms"], 3),
                              "bytes": v["bytes"]} for k, v in kernels.items()},

@@ -88,6 +88,11 @@ typedef struct truss_graph {
 #define TRUSS_PEEL_SPARSE 1 /* worklist: enqueue an edge when its support drops to k-2 */
 #define TRUSS_PEEL_DENSE 2  /* re-scan every live edge after each sub-round      */
 
+/* Membership test "(v, w) in E_G" while peeling (Algorithm 2, Step 8). */
+#define TRUSS_PROBE_AUTO 0    /* hash table                                      */
+#define TRUSS_PROBE_HASH 1    /* hash table over the edges, as Section 3.2 keeps E_G */
+#define TRUSS_PROBE_BSEARCH 2 /* binary search of the other endpoint's sorted row  */
+
 /* Scheduler used for TRUSS_SUP_AUTO / TRUSS_PEEL_AUTO decisions. */
 #define TRUSS_SCHED_PLAIN 0     /* fixed: bsearch support, dense sweep peeling  */
 #define TRUSS_SCHED_HEURISTIC 1 /* fixed thresholds                             */
@@ -101,23 +106,29 @@ typedef struct truss_options {
   const float *model;       /* (device) learned-scheduler weights, or NULL     */
   int64_t max_subrounds;    /* > 0: fail with TRUSS_E_INTERNAL past this many  */
   int32_t grid_blocks;      /* > 0: persistent-kernel workgroups (tuning)      */
-  int32_t reserved[7];
+  int32_t peel_probe;       /* TRUSS_PROBE_*                                    */
+  int32_t reserved[6];
 } truss_options;
 
 /* Filled when a stats pointer is passed (host). */
 typedef struct truss_stats {
   int64_t n, m;
-  int64_t triangles;  /* |triangles of G|                                    */
-  int32_t kmax;       /* largest truss number (0 when m = 0)                 */
-  int32_t levels;     /* non-empty k-classes visited                         */
-  int64_t subrounds;  /* frontier rounds over all levels                     */
-  int64_t peel_work;  /* adjacency entries scanned while peeling             */
-  double ms_build;    /* validation + CSR build + orientation                */
-  double ms_support;  /* support counting                                    */
-  double ms_peel;     /* peeling                                             */
+  int64_t triangles;        /* |triangles of G|                                  */
+  int32_t kmax;             /* largest truss number (0 when m = 0)               */
+  int32_t levels;           /* non-empty k-classes visited                       */
+  int64_t subrounds;        /* frontier rounds over all levels                   */
+  int64_t peel_work;        /* adjacency entries walked while peeling            */
+  double ms_build;          /* validation + CSR build + orientation              */
+  double ms_support;        /* support counting                                  */
+  double ms_peel;           /* peeling                                           */
   double ms_total;
-  int32_t sched_fallback; /* 1 if the learned model was absent or invalid    */
-  int32_t reserved[7];
+  int32_t sched_fallback;   /* 1 if the learned model was absent or invalid      */
+  int32_t launches;         /* peeling kernel launches (one more per row compaction) */
+  int64_t frontier_hist[6]; /* sub-rounds by frontier size: 1, 2-16, 17-256,
+                               257-4096, 4097-65536, larger                      */
+  int64_t heavy_rounds;     /* sub-rounds in which long walks were cut into pieces */
+  double ms_phase[6];       /* peeling time by phase: live-list sweep, level start,
+                               frontier rounds, unused, dense re-scan, unused     */
 } truss_stats;
 
 /* Fills *opts with defaults: AUTO strategies, heuristic scheduler. */

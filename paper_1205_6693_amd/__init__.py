@@ -26,6 +26,7 @@ E_INVAL, E_TOOBIG, E_ROWPTR, E_RANGE, E_SELFLOOP, E_UNSORTED, E_DUP, E_ASYM, E_N
 FMT_EDGES, FMT_CSR = 0, 1
 SUP_AUTO, SUP_HASH, SUP_BSEARCH, SUP_MERGE = 0, 1, 2, 3
 PEEL_AUTO, PEEL_SPARSE, PEEL_DENSE = 0, 1, 2
+PROBE_AUTO, PROBE_HASH, PROBE_BSEARCH = 0, 1, 2
 SCHED_PLAIN, SCHED_HEURISTIC, SCHED_LEARNED = 0, 1, 2
 
 
@@ -45,7 +46,8 @@ class Options(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int32), ("support_strategy", ctypes.c_int32),
                 ("peel_mode", ctypes.c_int32), ("scheduler", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("max_subrounds", ctypes.c_int64),
-                ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("grid_blocks", ctypes.c_int32), ("peel_probe", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Stats(ctypes.Structure):
@@ -54,10 +56,15 @@ class Stats(ctypes.Structure):
                 ("subrounds", ctypes.c_int64), ("peel_work", ctypes.c_int64),
                 ("ms_build", ctypes.c_double), ("ms_support", ctypes.c_double),
                 ("ms_peel", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("sched_fallback", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("sched_fallback", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("frontier_hist", ctypes.c_int64 * 6), ("heavy_rounds", ctypes.c_int64),
+                ("ms_phase", ctypes.c_double * 6)]
 
     def to_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["frontier_hist"] = list(self.frontier_hist)
+        d["ms_phase"] = list(self.ms_phase)
+        return d
 
 
 _lib = None
@@ -156,10 +163,11 @@ class Graph:
 
 
 def make_options(support_strategy=SUP_AUTO, peel_mode=PEEL_AUTO, scheduler=SCHED_HEURISTIC,
-                 model=None, max_subrounds=0, grid_blocks=0):
+                 model=None, max_subrounds=0, grid_blocks=0, peel_probe=PROBE_AUTO):
     o = Options()
     load_library().truss_default_options(ctypes.byref(o))
     o.support_strategy, o.peel_mode, o.scheduler = support_strategy, peel_mode, scheduler
+    o.peel_probe = peel_probe
     o.model = _ptr(model).value if model is not None else None
     o.max_subrounds, o.grid_blocks = max_subrounds, grid_blocks
     return o

@@ -67,7 +67,8 @@ int check_opts(const truss_options* o) {
   if (o->version != TRUSS_VERSION) { set_last_error("options version mismatch"); return TRUSS_E_INVAL; }
   if (o->support_strategy < TRUSS_SUP_AUTO || o->support_strategy > TRUSS_SUP_MERGE ||
       o->peel_mode < TRUSS_PEEL_AUTO || o->peel_mode > TRUSS_PEEL_DENSE ||
-      o->scheduler < TRUSS_SCHED_PLAIN || o->scheduler > TRUSS_SCHED_LEARNED) {
+      o->scheduler < TRUSS_SCHED_PLAIN || o->scheduler > TRUSS_SCHED_LEARNED ||
+      o->peel_probe < TRUSS_PROBE_AUTO || o->peel_probe > TRUSS_PROBE_BSEARCH) {
     set_last_error("option out of range");
     return TRUSS_E_INVAL;
   }
@@ -209,6 +210,10 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
     stats->ms_total = tm.ms(0, 3);
     stats->sched_fallback = fallback;
     stats->triangles = (int64_t)(tot / 3);
+    stats->launches = pr.launches;
+    stats->heavy_rounds = pr.heavy_rounds;
+    for (int b = 0; b < 6; ++b) stats->frontier_hist[b] = pr.hist[b];
+    for (int b = 0; b < 6; ++b) stats->ms_phase[b] = pr.phase_ms[b];
   }
   return TRUSS_OK;
 }
@@ -330,6 +335,11 @@ int truss_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_
       stats->ms_support += st.ms_support;
       stats->ms_peel += st.ms_peel;
       stats->ms_total += st.ms_total;
+      stats->triangles += st.triangles;
+      stats->launches += st.launches;
+      stats->heavy_rounds += st.heavy_rounds;
+      for (int b = 0; b < 6; ++b) stats->frontier_hist[b] += st.frontier_hist[b];
+      for (int b = 0; b < 6; ++b) stats->ms_phase[b] += st.ms_phase[b];
     }
   }
   return TRUSS_OK;

@@ -204,6 +204,32 @@ __global__ void k_ocsr(const int32_t* __restrict__ col, const int32_t* __restric
   }
 }
 
+// ---- edge hash table (Algorithm 2, Step 8) -------------------------------------------------
+
+__global__ void k_etab_clear(EdgeSlot* __restrict__ tab, int64_t size) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < size; i += (int64_t)gridDim.x * blockDim.x) {
+    tab[i].key = kEmptyKey;
+    tab[i].eid = -1;
+  }
+}
+
+__global__ void k_etab_insert(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
+                              EdgeSlot* __restrict__ tab, unsigned long long mask) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const unsigned long long key = edge_key(eu[e], ev[e]);
+  unsigned long long h = mix64(key) & mask;
+  // keys are distinct and the table is at most half full, so a free slot is found
+  while (atomicCAS(&tab[h].key, kEmptyKey, key) != kEmptyKey) h = (h + 1) & mask;
+  tab[h].eid = (int)e;
+}
+
+int64_t etab_size(int64_t m) {
+  int64_t size = 1024;
+  while (size < 2 * m) size <<= 1;
+  return size;
+}
+
 int read_err(const int* d_err, hipStream_t s) {
   int h = kNoErr;
   TRUSS_HIP(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -235,6 +261,8 @@ struct Layout {
   int64_t *opos;
   int32_t *rtmp;
   int64_t *stmp;
+  EdgeSlot* etab;
+  int64_t etab_n;
 };
 
 void carve(const truss_graph* g, Arena& a, Layout& L) {
@@ -248,6 +276,8 @@ void carve(const truss_graph* g, Arena& a, Layout& L) {
   L.oeid = a.take<int32_t>(m + 1);
   L.orow = a.take<int64_t>(n + 1);
   L.perm = edges ? a.take<int32_t>(m + 1) : nullptr;
+  L.etab_n = etab_size(m);
+  L.etab = a.take<EdgeSlot>((size_t)L.etab_n);
   L.row_ptr = edges ? a.take<int64_t>(n + 1) : nullptr;
   // temporaries (could alias peeling state; kept separate for clarity)
   L.kf = a.take<int32_t>(m2 + 1);
@@ -355,6 +385,15 @@ int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStr
   dg.orow = L.orow;
   dg.ocol = L.ocol;
   dg.oeid = L.oeid;
+  // edge hash table for the membership tests of peeling
+  hipLaunchKernelGGL(k_etab_clear, dim3(grid_for(L.etab_n) < 65536 ? grid_for(L.etab_n) : 65536), dim3(kT), 0, s,
+                     L.etab, L.etab_n);
+  if (m > 0)
+    hipLaunchKernelGGL(k_etab_insert, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.etab,
+                       (unsigned long long)(L.etab_n - 1));
+  TRUSS_HIP(hipGetLastError());
+  dg.etab = L.etab;
+  dg.etab_mask = (unsigned long long)(L.etab_n - 1);
   return TRUSS_OK;
 }
 

@@ -107,4 +107,42 @@ __device__ __forceinline__ IdxT lower_bound_i32(const int* __restrict__ a, IdxT 
   return lo;
 }
 
+// ---- edge hash table ------------------------------------------------------------
+// The membership test of Algorithm 2, Step 8 ("(v, w) in E_G") through a
+// hashtable over E_G (Section 3.2): open addressing with linear probing, key
+// (min << 32 | max), value the canonical edge id.  At most half full.
+struct EdgeSlot {
+  unsigned long long key;
+  int eid;
+  int pad;
+};
+constexpr unsigned long long kEmptyKey = ~0ULL;
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long k) {
+  // MurmurHash3 64-bit finaliser
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdULL;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ULL;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ unsigned long long edge_key(int a, int b) {
+  const unsigned lo = (unsigned)(a < b ? a : b), hi = (unsigned)(a < b ? b : a);
+  return ((unsigned long long)lo << 32) | hi;
+}
+
+// edge id of {a, b}, or -1 if it is not an edge
+__device__ __forceinline__ int edge_lookup(const EdgeSlot* __restrict__ tab, unsigned long long mask, int a, int b) {
+  const unsigned long long key = edge_key(a, b);
+  unsigned long long h = mix64(key) & mask;
+  for (;;) {
+    const unsigned long long k = tab[h].key;
+    if (k == key) return tab[h].eid;
+    if (k == kEmptyKey) return -1;
+    h = (h + 1) & mask;
+  }
+}
+
 }  // namespace truss

@@ -63,7 +63,8 @@ struct DevGraph {
   int32_t* ocol = nullptr;           // m out-neighbours, ascending
   int32_t* oeid = nullptr;           // m edge ids of oriented entries
   int32_t* perm = nullptr;           // m canonical edge -> input index (EDGES only)
-  int max_outdeg = 0;
+  struct EdgeSlot* etab = nullptr;   // hash table over the edges
+  unsigned long long etab_mask = 0;  // table size - 1 (a power of two >= 2m)
 };
 
 // Build: validation + canonical edge ids + symmetric and oriented CSR.
@@ -80,8 +81,10 @@ int compute_support(const DevGraph& dg, int strategy, int2* sr, Arena& a, hipStr
 struct PeelResult {
   int32_t kmax = 0, levels = 0;
   int64_t subrounds = 0, work = 0;
-  int32_t err = 0;
-  int32_t fallback = 0;
+  int32_t launches = 0;
+  int64_t heavy_rounds = 0;
+  int64_t hist[6] = {0, 0, 0, 0, 0, 0};
+  double phase_ms[6] = {0, 0, 0, 0, 0, 0};
 };
 size_t peel_workspace(const DevGraph& dg, Arena& a);
 int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss_canon, Arena& a,

@@ -15,13 +15,24 @@
 // Triangles through a frontier edge e = (u, v) are found as in Algorithm 2,
 // Steps 6-8: walk the adjacency row of the endpoint with the shorter live row,
 // and look each neighbour w up in the other endpoint's sorted row by binary
-// search.  Deleted edges are only marked (Section 3.1), and the rows are
-// compacted in place whenever the live edge count has halved.
+// search.  Deleted edges are only marked (Section 3.1); the rows are compacted
+// in place whenever the live edge count has halved.
 //
-// The whole loop runs in one persistent cooperative kernel.  Phases are
-// separated by a grid barrier; the last workgroup to arrive runs the control
-// step (next phase, next level k = max(k+1, min live support + 2), queue sizes)
-// before releasing the others, so the host is not involved until the end.
+// The level loop runs in a persistent cooperative kernel, one 1024-thread
+// workgroup per compute unit.  Phases are separated by a grid barrier; the last
+// workgroup to arrive runs the control step (next phase, next level
+// k = max(k+1, min live support + 2), queue sizes) before releasing the others.
+// The kernel returns to the host only to compact the rows (a separate kernel)
+// or when every edge is removed.
+//
+// Memory coherence: the L2 caches of the XCDs are not coherent with each
+// other, and an agent-scope fence writes back and invalidates a whole L2.  The
+// barrier therefore uses no fences: every value that one phase writes and a
+// later phase of another workgroup reads (queues, live lists, round stamps,
+// supports, pieces) is written and read with agent-scope relaxed atomics, which
+// go to the coherent level, and each lane waits for its outstanding memory
+// operations before its workgroup arrives.  Adjacency rows, offsets and row
+// lengths are immutable inside a launch and use ordinary cached loads.
 //
 // Frontier modes per level: SPARSE enqueues an edge the moment its support
 // drops from k-1 to k-2 (the queue of Section 3.1); DENSE re-scans the live
@@ -33,19 +44,20 @@ namespace truss {
 
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = 1024;
 constexpr int kWaves = kT / kWave;
-constexpr int kHeavy = 2048;   // frontier edges with a longer walk are split into pieces
-constexpr int kPiece = 1024;   // adjacency entries per piece
+constexpr int kLight = 128;   // frontier edges with a longer walk are cut into pieces
+constexpr int kPiece = 512;   // adjacency entries per piece
 constexpr int kIntMax = 0x7fffffff;
+constexpr int kHistBins = 6;
 
 enum Phase : int {
-  PH_SWEEP = 0,   // compact the live-edge list, minimum live support
-  PH_START = 1,   // level start: collect live edges with sup <= k-2
-  PH_PROC = 2,    // destroy triangles of F_r (light edges; heavy ones queued)
-  PH_HEAVY = 3,   // split walks of heavy frontier edges
-  PH_DENSE = 4,   // dense mode: collect next frontier by re-scan
-  PH_COMPACT = 5, // drop removed entries from the adjacency rows
+  PH_SWEEP = 0,    // compact the live-edge list, minimum live support
+  PH_START = 1,    // level start: collect live edges with sup <= k-2
+  PH_PROC = 2,     // destroy the triangles of F_r
+  PH_UNUSED = 3,
+  PH_DENSE = 4,    // dense mode: collect the next frontier by re-scan
+  PH_COMPACT = 5,  // return to the host: drop removed entries from the rows
   PH_DONE = 6
 };
 
@@ -59,8 +71,8 @@ struct alignas(256) PeelCtl {
   int w_qlen;
   int w_alive;
   int w_minsup;
-  int w_pfetch;   // piece fetch counter
-  int pad2;
+  int w_pfetch;
+  int w_lightdone;  // waves that finished their own frontier edges this round
   unsigned long long w_pieces;  // pieces appended this round (may exceed capacity)
   unsigned long long w_work;
   int pad3[54];
@@ -73,75 +85,101 @@ struct alignas(256) PeelCtl {
   int acur;
   int first;
   int mode;
-  int pcount;     // pieces to process in PH_HEAVY
-  int pcap;       // piece-list capacity
-  long long removed_level;
-  long long csr_live;
+  int pcap;
   int kmax;
   int levels;
+  long long removed_level;
+  long long csr_live;
   long long subrounds;
-  long long work;
+  long long heavy_rounds;
+  long long max_subrounds;
+  long long hist[kHistBins];
+  unsigned long long t_last;            // wall clock at the previous barrier
+  unsigned long long t_phase[8];        // time spent per phase (100 MHz ticks)
   int err;
   int abort;
-  long long max_subrounds;
   int force_mode;
+  int launches;
 };
 
 struct PeelArgs {
   int32_t n;
   int64_t m;
   const int64_t* row_ptr;
-  int32_t* col;
-  int32_t* seid;
-  int32_t* rlen;
+  const int32_t* col;
+  const int32_t* seid;
+  const int32_t* rlen;
   const int32_t* eu;
   const int32_t* ev;
   int2* sr;
   int32_t* truss;
   int32_t* alist[2];
   int32_t* fq[2];
-  int32_t* pe;   // piece: frontier edge
-  int32_t* pb;   // piece: endpoint whose row is searched
-  int64_t* pj;   // piece: first adjacency entry
-  int32_t* pn;   // piece: entry count
+  unsigned long long* pslot;  // pieces: ((edge + 1) << 32) | piece index, 0 = empty
+  const EdgeSlot* etab;       // edge hash table
+  unsigned long long etab_mask;
+  int probe;                  // 0: hash table lookup, 1: binary search of the row
   PeelCtl* ctl;
 };
 
-__device__ __forceinline__ int ld(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-__device__ __forceinline__ long long ld(const long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld(const unsigned long long* p) {
+// ---- coherent (agent-scope relaxed) accesses ---------------------------------------
+template <typename T>
+__device__ __forceinline__ T ldc(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
-__device__ __forceinline__ void st(T* p, T v) {
+__device__ __forceinline__ void stc(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ int2 ldc2(const int2* p) {
+  const unsigned long long x = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  return make_int2((int)(uint32_t)x, (int)(uint32_t)(x >> 32));
+}
+__device__ __forceinline__ int ldc_stamp(const int2* p) { return ldc(&p->y); }
+__device__ __forceinline__ void stc_stamp(int2* p, int v) { stc(&p->y, v); }
 
-// ---- control step: runs on one thread of the last workgroup at each barrier ----------------
+// wait until this lane's global loads, stores and atomics have completed
+__device__ __forceinline__ void mem_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ int hist_bin(long long q) {
+  return q <= 1 ? 0 : q <= 16 ? 1 : q <= 256 ? 2 : q <= 4096 ? 3 : q <= 65536 ? 4 : 5;
+}
+
+// ---- control step: one thread of the last workgroup to reach a barrier -----------------------
 __device__ void control_step(PeelCtl* c) {
-  int phase = ld(&c->phase);
-  const int r = ld(&c->r);
-  long long subrounds = ld(&c->subrounds);
-  const long long maxsr = ld(&c->max_subrounds);
-  auto next_round = [&](void) {
-    const int q = ld(&c->w_qlen);
-    st(&c->w_qlen, 0);
-    st(&c->w_fetch, 0);
+  int phase = ldc(&c->phase);
+  {
+    const unsigned long long now = wall_clock64();
+    const unsigned long long last = ldc(&c->t_last);
+    if (last != 0 && phase >= 0 && phase < 8) stc(&c->t_phase[phase], ldc(&c->t_phase[phase]) + (now - last));
+    stc(&c->t_last, now);
+  }
+  const int r = ldc(&c->r);
+  long long subrounds = ldc(&c->subrounds);
+  const long long maxsr = ldc(&c->max_subrounds);
+  auto begin_round = [&](int q) {
+    stc(&c->qlen, q);
+    subrounds += 1;
+    stc(&c->subrounds, subrounds);
+    const int b = hist_bin(q);
+    stc(&c->hist[b], ldc(&c->hist[b]) + 1);
+    phase = PH_PROC;
+  };
+  auto next_round = [&]() {
+    const int q = ldc(&c->w_qlen);
+    stc(&c->w_qlen, 0);
+    stc(&c->w_fetch, 0);
     if (q > 0) {
-      st(&c->qlen, q);
-      st(&c->r, r + 1);
-      st(&c->removed_level, ld(&c->removed_level) + q);
-      subrounds += 1;
-      st(&c->subrounds, subrounds);
-      phase = PH_PROC;
+      stc(&c->r, r + 1);
+      stc(&c->removed_level, ldc(&c->removed_level) + q);
+      begin_round(q);
     } else {
-      // level finished: compact rows when the live count has halved
-      const long long alive_after = (long long)ld(&c->acnt) - ld(&c->removed_level);
-      const long long live = ld(&c->csr_live);
+      // level finished: compact the rows when the live count has halved
+      const long long alive_after = (long long)ldc(&c->acnt) - ldc(&c->removed_level);
+      const long long live = ldc(&c->csr_live);
       if (alive_after > 0 && alive_after * 2 < live) {
-        st(&c->csr_live, alive_after);
+        stc(&c->csr_live, alive_after);
         phase = PH_COMPACT;
       } else {
         phase = PH_SWEEP;
@@ -150,56 +188,48 @@ __device__ void control_step(PeelCtl* c) {
   };
   switch (phase) {
     case PH_SWEEP: {
-      const int alive = ld(&c->w_alive);
-      const int minsup = ld(&c->w_minsup);
-      st(&c->w_alive, 0);
-      st(&c->w_minsup, kIntMax);
-      st(&c->acnt, alive);
-      st(&c->acur, ld(&c->acur) ^ 1);
-      st(&c->first, 0);
-      if (alive == 0) { phase = PH_DONE; break; }
-      int k = ld(&c->k) + 1;
+      const int alive = ldc(&c->w_alive);
+      const int minsup = ldc(&c->w_minsup);
+      stc(&c->w_alive, 0);
+      stc(&c->w_minsup, kIntMax);
+      stc(&c->acnt, alive);
+      stc(&c->acur, ldc(&c->acur) ^ 1);
+      stc(&c->first, 0);
+      if (alive == 0) {
+        phase = PH_DONE;
+        break;
+      }
+      int k = ldc(&c->k) + 1;
       if (minsup + 2 > k) k = minsup + 2;
-      st(&c->k, k);
-      st(&c->kmax, k);
-      st(&c->levels, ld(&c->levels) + 1);
-      st(&c->r, r + 1);
-      st(&c->removed_level, 0LL);
-      const int fm = ld(&c->force_mode);
-      st(&c->mode, fm == TRUSS_PEEL_DENSE ? (int)TRUSS_PEEL_DENSE : (int)TRUSS_PEEL_SPARSE);
-      st(&c->w_qlen, 0);
-      st(&c->w_fetch, 0);
+      stc(&c->k, k);
+      stc(&c->kmax, k);
+      stc(&c->levels, ldc(&c->levels) + 1);
+      stc(&c->r, r + 1);
+      stc(&c->removed_level, 0LL);
+      const int fm = ldc(&c->force_mode);
+      stc(&c->mode, fm == TRUSS_PEEL_DENSE ? (int)TRUSS_PEEL_DENSE : (int)TRUSS_PEEL_SPARSE);
+      stc(&c->w_qlen, 0);
+      stc(&c->w_fetch, 0);
       phase = PH_START;
       break;
     }
     case PH_START: {
-      const int q = ld(&c->w_qlen);
-      st(&c->w_qlen, 0);
-      st(&c->w_fetch, 0);
-      st(&c->qlen, q);
-      st(&c->removed_level, (long long)q);
-      subrounds += 1;
-      st(&c->subrounds, subrounds);
-      phase = q > 0 ? PH_PROC : PH_SWEEP;
+      const int q = ldc(&c->w_qlen);
+      stc(&c->w_qlen, 0);
+      stc(&c->w_fetch, 0);
+      stc(&c->removed_level, (long long)q);
+      if (q > 0) begin_round(q);
+      else phase = PH_SWEEP;
       break;
     }
-    case PH_PROC:
-    case PH_HEAVY: {
-      if (phase == PH_PROC) {
-        const unsigned long long pw = ld(&c->w_pieces);
-        const int cap = ld(&c->pcap);
-        const int pc = pw > (unsigned long long)cap ? cap : (int)pw;
-        st(&c->w_pieces, 0ULL);
-        st(&c->w_pfetch, 0);
-        if (pc > 0) {
-          st(&c->pcount, pc);
-          phase = PH_HEAVY;
-          break;
-        }
-      }
-      if (ld(&c->mode) == TRUSS_PEEL_DENSE) {
-        st(&c->w_qlen, 0);
-        st(&c->w_fetch, 0);
+    case PH_PROC: {
+      if (ldc(&c->w_pieces) != 0ULL) stc(&c->heavy_rounds, ldc(&c->heavy_rounds) + 1);
+      stc(&c->w_pieces, 0ULL);
+      stc(&c->w_pfetch, 0);
+      stc(&c->w_lightdone, 0);
+      if (ldc(&c->mode) == TRUSS_PEEL_DENSE) {
+        stc(&c->w_qlen, 0);
+        stc(&c->w_fetch, 0);
         phase = PH_DENSE;
         break;
       }
@@ -209,49 +239,45 @@ __device__ void control_step(PeelCtl* c) {
     case PH_DENSE:
       next_round();
       break;
-    case PH_COMPACT:
-      phase = PH_SWEEP;
-      break;
     default:
       phase = PH_DONE;
   }
   if (maxsr > 0 && subrounds > maxsr && phase != PH_DONE) {
-    st(&c->err, (int)TRUSS_E_INTERNAL);
+    stc(&c->err, (int)TRUSS_E_INTERNAL);
     phase = PH_DONE;
   }
-  st(&c->phase, phase);
+  stc(&c->phase, phase);
 }
 
-// Grid barrier; the last workgroup to arrive runs control_step before release.
-// Returns false if the wait timed out (the kernel then winds down).
+// Grid barrier without cache maintenance (see the coherence note above); the
+// last workgroup to arrive runs control_step before release.  Returns false if
+// the wait timed out, and the kernel then winds down.
 __device__ bool phase_barrier(PeelCtl* c) {
   __shared__ int s_ok;
+  mem_wait();
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned gen = ldc(&c->bar_gen);
+    const unsigned prev = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == gridDim.x - 1) {
-      __threadfence();
       control_step(c);
-      __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      stc(&c->bar_count, 0u);
+      mem_wait();
+      __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (__hip_atomic_load(&c->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+      while (ldc(&c->bar_gen) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (ldc(&c->abort)) { ok = 0; break; }
         // 100 MHz constant clock: give up after 30 s
         if (wall_clock64() - t0 > 3000000000ULL) {
-          __hip_atomic_store(&c->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          stc(&c->abort, 1);
           ok = 0;
           break;
         }
       }
     }
-    __threadfence();
     s_ok = ok;
   }
   __syncthreads();
@@ -260,7 +286,7 @@ __device__ bool phase_barrier(PeelCtl* c) {
 
 __device__ __forceinline__ bool removed_at(int rnd, int r) { return rnd != 0 && rnd < r; }
 
-// One adjacency entry j of the walk of frontier edge e = (a, b).  Returns the
+// One adjacency entry j of the walk of frontier edge e = (a, b).  Outputs the
 // (up to two) edges whose support crossed k-1 -> k-2 and must be enqueued.
 __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int32_t b, int64_t j, int r, int l, int k,
                                               bool sparse, int32_t& f1, int32_t& f2) {
@@ -269,14 +295,20 @@ __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int3
   const int32_t w = P.col[j];
   if (w == b) return;
   const int32_t e1 = P.seid[j];
-  const int rnd1 = P.sr[e1].y;
+  const int rnd1 = ldc_stamp(&P.sr[e1]);
   if (removed_at(rnd1, r)) return;
-  const int64_t rb = P.row_ptr[b];
-  const int64_t re = rb + P.rlen[b];
-  const int64_t p = lower_bound_i32<int64_t>(P.col, rb, re, w);
-  if (p >= re || P.col[p] != w) return;
-  const int32_t e2 = P.seid[p];
-  const int rnd2 = P.sr[e2].y;
+  int32_t e2;
+  if (P.probe == 0) {
+    e2 = edge_lookup(P.etab, P.etab_mask, b, w);
+    if (e2 < 0) return;
+  } else {
+    const int64_t rb = P.row_ptr[b];
+    const int64_t re = rb + P.rlen[b];
+    const int64_t p = lower_bound_i32<int64_t>(P.col, rb, re, w);
+    if (p >= re || P.col[p] != w) return;
+    e2 = P.seid[p];
+  }
+  const int rnd2 = ldc_stamp(&P.sr[e2]);
   if (removed_at(rnd2, r)) return;
   // the triangle belongs to its frontier edge of smallest id
   if (rnd1 == r && e1 < e) return;
@@ -284,7 +316,7 @@ __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int3
   if (rnd1 != r) {
     const int old = atomicSub(&P.sr[e1].x, 1);
     if (sparse && old == l + 1) {
-      P.sr[e1].y = r + 1;
+      stc_stamp(&P.sr[e1], r + 1);
       P.truss[e1] = k;
       f1 = e1;
     }
@@ -292,7 +324,7 @@ __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int3
   if (rnd2 != r) {
     const int old = atomicSub(&P.sr[e2].x, 1);
     if (sparse && old == l + 1) {
-      P.sr[e2].y = r + 1;
+      stc_stamp(&P.sr[e2], r + 1);
       P.truss[e2] = k;
       f2 = e2;
     }
@@ -301,9 +333,9 @@ __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int3
 
 __device__ __forceinline__ void push_next(const PeelArgs& P, int32_t* q, int32_t f1, int32_t f2) {
   const int p1 = wave_append(&P.ctl->w_qlen, f1 >= 0);
-  if (f1 >= 0) q[p1] = f1;
+  if (f1 >= 0) stc(&q[p1], f1);
   const int p2 = wave_append(&P.ctl->w_qlen, f2 >= 0);
-  if (f2 >= 0) q[p2] = f2;
+  if (f2 >= 0) stc(&q[p2], f2);
 }
 
 __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
@@ -319,16 +351,16 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
   unsigned long long my_work = 0;
 
   for (;;) {
-    const int phase = ld(&c->phase);
-    if (phase == PH_DONE) break;
-    const int k = ld(&c->k);
+    const int phase = ldc(&c->phase);
+    if (phase == PH_DONE || phase == PH_COMPACT) break;
+    const int k = ldc(&c->k);
     const int l = k - 2;
-    const int r = ld(&c->r);
-    const int acur = ld(&c->acur);
+    const int r = ldc(&c->r);
+    const int acur = ldc(&c->acur);
     if (phase == PH_SWEEP) {
       // live-edge list of the new level; minimum live support
-      const int first = ld(&c->first);
-      const int64_t cnt = first ? P.m : (int64_t)ld(&c->acnt);
+      const int first = ldc(&c->first);
+      const int64_t cnt = first ? P.m : (int64_t)ldc(&c->acnt);
       const int32_t* A = P.alist[acur];
       int32_t* B = P.alist[acur ^ 1];
       int mins = kIntMax;
@@ -337,19 +369,19 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         bool live = false;
         int32_t e = 0;
         if (i < cnt) {
-          e = first ? (int32_t)i : A[i];
-          const int2 s = P.sr[e];
+          e = first ? (int32_t)i : ldc(&A[i]);
+          const int2 s = ldc2(&P.sr[e]);
           live = s.y == 0;
           if (live && s.x < mins) mins = s.x;
         }
         const int pos = wave_append(&c->w_alive, live);
-        if (live) B[pos] = e;
+        if (live) stc(&B[pos], e);
       }
       mins = wave_min(mins);
       if (lane == 0 && mins != kIntMax) atomicMin(&c->w_minsup, mins);
     } else if (phase == PH_START || phase == PH_DENSE) {
       // collect live edges with sup <= k-2 (level start, or dense re-scan)
-      const int64_t cnt = ld(&c->acnt);
+      const int64_t cnt = ldc(&c->acnt);
       const int32_t* A = P.alist[acur];
       const int stamp = phase == PH_START ? r : r + 1;
       int32_t* Q = P.fq[stamp & 1];
@@ -358,22 +390,25 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         bool take = false;
         int32_t e = 0;
         if (i < cnt) {
-          e = A[i];
-          const int2 s = P.sr[e];
+          e = ldc(&A[i]);
+          const int2 s = ldc2(&P.sr[e]);
           take = s.y == 0 && s.x <= l;
           if (take) {
-            P.sr[e].y = stamp;
+            stc_stamp(&P.sr[e], stamp);
             P.truss[e] = k;
           }
         }
         const int pos = wave_append(&c->w_qlen, take);
-        if (take) Q[pos] = e;
+        if (take) stc(&Q[pos], e);
       }
     } else if (phase == PH_PROC) {
-      const int qn = ld(&c->qlen);
-      const bool sparse = ld(&c->mode) == TRUSS_PEEL_SPARSE;
+      const int qn = ldc(&c->qlen);
+      const bool sparse = ldc(&c->mode) == TRUSS_PEEL_SPARSE;
       const int32_t* Q = P.fq[r & 1];
       int32_t* Qn = P.fq[(r + 1) & 1];
+      const unsigned long long cap = (unsigned long long)ldc(&c->pcap);
+      // (1) frontier edges in chunks of 64: short walks flattened across the
+      // wave, long walks cut into pieces that any wave may take
       for (;;) {
         int base = 0;
         if (lane == 0) base = atomicAdd(&c->w_fetch, kWave);
@@ -384,7 +419,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         int32_t e = 0, a = 0, b = 0;
         int work = 0;
         if (valid) {
-          e = Q[i];
+          e = ldc(&Q[i]);
           const int32_t u = P.eu[e], v = P.ev[e];
           const int du = P.rlen[u], dv = P.rlen[v];
           const bool ua = du < dv || (du == dv && u < v);
@@ -392,37 +427,32 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
           b = ua ? v : u;
           work = ua ? du : dv;
         }
-        // heavy walks are cut into pieces for PH_HEAVY; pieces past the list's
-        // capacity are walked here
-        const bool heavy = work > kHeavy;
-        int64_t inl_lo = 0, inl_hi = 0;
+        const int64_t ra = P.row_ptr[a];
+        const bool heavy = work > kLight;
         if (ballot(heavy)) {
+          int64_t inl_lo = 0, inl_hi = 0;
           const int np = heavy ? (work + kPiece - 1) / kPiece : 0;
           const int pinc = wave_inclusive_sum(np);
           const int ptot = __shfl(pinc, kWave - 1, kWave);
           unsigned long long pbase = 0;
           if (lane == 0) pbase = atomicAdd(&c->w_pieces, (unsigned long long)ptot);
           pbase = __shfl(pbase, 0, kWave);
-          const int cap = ld(&c->pcap);
-          const int64_t ra = P.row_ptr[a];
           if (heavy) {
             const unsigned long long first = pbase + (unsigned long long)(pinc - np);
             for (int q = 0; q < np; ++q) {
-              const int64_t j0 = ra + (int64_t)q * kPiece;
-              const int len = work - q * kPiece < kPiece ? work - q * kPiece : kPiece;
-              if (first + q < (unsigned long long)cap) {
-                P.pe[first + q] = e;
-                P.pb[first + q] = b;
-                P.pj[first + q] = j0;
-                P.pn[first + q] = len;
+              const unsigned long long slot = first + (unsigned long long)q;
+              if (slot < cap) {
+                stc(&P.pslot[slot], ((unsigned long long)(e + 1) << 32) | (unsigned)q);
               } else {
+                const int64_t j0 = ra + (int64_t)q * kPiece;
+                const int len = work - q * kPiece < kPiece ? work - q * kPiece : kPiece;
                 if (inl_hi == 0) inl_lo = j0;
                 inl_hi = j0 + len;
               }
             }
           }
           work = heavy ? 0 : work;
-          // overflow pieces: the wave walks them one heavy edge at a time
+          // pieces that found no slot: this wave walks them, one edge at a time
           uint64_t om = ballot(inl_hi > inl_lo);
           while (om) {
             const int src = __builtin_ctzll(om);
@@ -434,7 +464,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
               if (j0 + lane < hi) process_entry(P, oe, ob, j0 + lane, r, l, k, sparse, f1, f2);
               push_next(P, Qn, f1, f2);
             }
-            my_work += (unsigned long long)(hi - lo);
+            if (lane == 0) my_work += (unsigned long long)(hi - lo);
           }
         }
         const int inc = wave_inclusive_sum(work);
@@ -443,14 +473,14 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         if (lane == 0) s_pre[wv][0] = 0;
         s_e[wv][lane] = e;
         s_b[wv][lane] = b;
-        s_base[wv][lane] = P.row_ptr[a];
+        s_base[wv][lane] = ra;
         wave_sync();
-        my_work += (unsigned long long)W;
+        if (lane == 0) my_work += (unsigned long long)W;
         for (int t0 = 0; t0 < W; t0 += kWave) {
           const int t = t0 + lane;
           int32_t f1 = -1, f2 = -1;
           if (t < W) {
-            int lo = 0, hi = kWave - 1;
+            int lo = 0, hi = kWave - 1;  // last lane whose range starts at or before t
             while (lo < hi) {
               const int mid = (lo + hi + 1) >> 1;
               if (s_pre[wv][mid] <= t) lo = mid; else hi = mid - 1;
@@ -462,62 +492,92 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         }
         wave_sync();
       }
-    } else if (phase == PH_HEAVY) {
-      const int pc = ld(&c->pcount);
-      const bool sparse = ld(&c->mode) == TRUSS_PEEL_SPARSE;
-      int32_t* Qn = P.fq[(r + 1) & 1];
+      // (2) pieces: every wave takes pieces until all waves are done with (1)
+      // and every claimed piece has been taken.  A piece is published by a
+      // single 64-bit store and cleared by the wave that takes it.
+      mem_wait();
+      if (lane == 0) atomicAdd(&c->w_lightdone, 1);
       for (;;) {
         int q = 0;
         if (lane == 0) q = atomicAdd(&c->w_pfetch, 1);
         q = __shfl(q, 0, kWave);
-        if (q >= pc) break;
-        const int32_t e = P.pe[q], b = P.pb[q];
-        const int64_t j0 = P.pj[q];
-        const int len = P.pn[q];
+        unsigned long long pv = 0;
+        for (;;) {
+          if ((unsigned long long)q < cap) pv = ldc(&P.pslot[q]);
+          if (pv != 0) break;
+          const unsigned long long claimed = ldc(&c->w_pieces);
+          const unsigned long long limit = claimed < cap ? claimed : cap;
+          if (ldc(&c->w_lightdone) == (int)nwaves && (unsigned long long)q >= limit) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        pv = __shfl(pv, 0, kWave);
+        if (pv == 0) break;
+        if (lane == 0) stc(&P.pslot[q], 0ULL);
+        const int32_t e = (int32_t)(pv >> 32) - 1;
+        const int qi = (int)(pv & 0xffffffffu);
+        const int32_t u = P.eu[e], v = P.ev[e];
+        const int du = P.rlen[u], dv = P.rlen[v];
+        const bool ua = du < dv || (du == dv && u < v);
+        const int32_t a = ua ? u : v, b = ua ? v : u;
+        const int work = ua ? du : dv;
+        const int64_t j0 = P.row_ptr[a] + (int64_t)qi * kPiece;
+        const int len = work - qi * kPiece < kPiece ? work - qi * kPiece : kPiece;
         for (int t0 = 0; t0 < len; t0 += kWave) {
           int32_t f1 = -1, f2 = -1;
           if (t0 + lane < len) process_entry(P, e, b, j0 + t0 + lane, r, l, k, sparse, f1, f2);
           push_next(P, Qn, f1, f2);
         }
-        my_work += (unsigned long long)len;
-      }
-    } else if (phase == PH_COMPACT) {
-      // stable in-place compaction of every row to its live entries
-      for (int64_t v = gwave; v < P.n; v += nwaves) {
-        const int64_t rb = P.row_ptr[v];
-        const int len = P.rlen[v];
-        int wpos = 0;
-        for (int c0 = 0; c0 < len; c0 += kWave) {
-          const int i = c0 + lane;
-          int32_t x = 0, ed = 0;
-          bool keep = false;
-          if (i < len) {
-            x = P.col[rb + i];
-            ed = P.seid[rb + i];
-            keep = P.sr[ed].y == 0;
-          }
-          const uint64_t km = ballot(keep);
-          if (keep) {
-            const int64_t dst = rb + wpos + rank_below(km);
-            P.col[dst] = x;
-            P.seid[dst] = ed;
-          }
-          wpos += __popcll(km);
-        }
-        if (lane == 0) P.rlen[v] = wpos;
+        if (lane == 0) my_work += (unsigned long long)len;
       }
     }
     if (!phase_barrier(c)) break;
   }
-  // statistics
   my_work = wave_sum(my_work);
   if (lane == 0 && my_work) atomicAdd(&c->w_work, my_work);
 }
 
+// Stable in-place compaction of every row to its live entries (a wavefront a row).
+__global__ void __launch_bounds__(256) k_compact(const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
+                                                 int32_t* __restrict__ seid, int32_t* __restrict__ rlen, int32_t n,
+                                                 const int2* __restrict__ sr, PeelCtl* c) {
+  const int lane = lane_id();
+  const int64_t gw = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  if (gw == 0 && lane == 0) {
+    c->phase = PH_SWEEP;
+    c->t_last = 0;
+  }
+  for (int64_t v = gw; v < n; v += nw) {
+    const int64_t rb = row_ptr[v];
+    const int len = rlen[v];
+    int wpos = 0;
+    for (int c0 = 0; c0 < len; c0 += kWave) {
+      const int i = c0 + lane;
+      int32_t x = 0, ed = 0;
+      bool keep = false;
+      if (i < len) {
+        x = col[rb + i];
+        ed = seid[rb + i];
+        keep = sr[ed].y == 0;
+      }
+      const uint64_t km = ballot(keep);
+      if (keep) {
+        const int64_t dst = rb + wpos + rank_below(km);
+        col[dst] = x;
+        seid[dst] = ed;
+      }
+      wpos += __popcll(km);
+    }
+    if (lane == 0) rlen[v] = wpos;
+  }
+}
+
 __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int32_t* __restrict__ rlen, int32_t n,
-                            int64_t m, long long max_subrounds, int force_mode, int pcap) {
+                            int64_t m, long long max_subrounds, int force_mode, int pcap,
+                            unsigned long long* __restrict__ pslot) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) rlen[i] = (int32_t)(row_ptr[i + 1] - row_ptr[i]);
+  if (i < pcap) pslot[i] = 0ULL;
   if (i == 0) {
     c->bar_count = 0;
     c->bar_gen = 0;
@@ -525,9 +585,10 @@ __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int
     c->w_qlen = 0;
     c->w_alive = 0;
     c->w_minsup = kIntMax;
-    c->w_pieces = 0ULL;
     c->w_pfetch = 0;
-    c->w_work = 0;
+    c->w_lightdone = 0;
+    c->w_pieces = 0ULL;
+    c->w_work = 0ULL;
     c->phase = PH_SWEEP;
     c->k = 1;
     c->r = 0;
@@ -536,18 +597,21 @@ __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int
     c->acur = 0;
     c->first = 1;
     c->mode = TRUSS_PEEL_SPARSE;
-    c->pcount = 0;
     c->pcap = pcap;
-    c->removed_level = 0;
-    c->csr_live = m;
     c->kmax = 0;
     c->levels = 0;
+    c->removed_level = 0;
+    c->csr_live = m;
     c->subrounds = 0;
-    c->work = 0;
+    c->heavy_rounds = 0;
+    c->max_subrounds = max_subrounds;
+    for (int b = 0; b < kHistBins; ++b) c->hist[b] = 0;
+    c->t_last = 0;
+    for (int b = 0; b < 8; ++b) c->t_phase[b] = 0;
     c->err = 0;
     c->abort = 0;
-    c->max_subrounds = max_subrounds;
     c->force_mode = force_mode;
+    c->launches = 0;
   }
 }
 
@@ -556,8 +620,7 @@ struct PeelLayout {
   int32_t* rlen;
   int32_t* alist[2];
   int32_t* fq[2];
-  int32_t *pe, *pb, *pn;
-  int64_t* pj;
+  unsigned long long* pslot;
   int pcap;
 };
 
@@ -568,10 +631,7 @@ void carve(const DevGraph& dg, Arena& a, PeelLayout& L) {
   for (int i = 0; i < 2; ++i) L.alist[i] = a.take<int32_t>(m + 1);
   for (int i = 0; i < 2; ++i) L.fq[i] = a.take<int32_t>(m + 1);
   L.pcap = (int)(m < (1 << 22) ? m : (1 << 22));
-  L.pe = a.take<int32_t>(L.pcap + 1);
-  L.pb = a.take<int32_t>(L.pcap + 1);
-  L.pn = a.take<int32_t>(L.pcap + 1);
-  L.pj = a.take<int64_t>(L.pcap + 1);
+  L.pslot = a.take<unsigned long long>(L.pcap + 1);
 }
 
 int g_peel_blocks = 0;
@@ -593,10 +653,21 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
   if (dg.m == 0) return TRUSS_OK;
   const int force = opts ? opts->peel_mode : TRUSS_PEEL_AUTO;
   const long long maxsr = opts ? opts->max_subrounds : 0;
-  const int64_t initn = dg.n > 1 ? dg.n : 1;
-  hipLaunchKernelGGL(k_peel_init, dim3((unsigned)((initn + kT - 1) / kT)), dim3(kT), 0, s, L.ctl, dg.row_ptr, L.rlen,
-                     dg.n, dg.m, maxsr, force, L.pcap);
-  if (g_peel_blocks == 0) g_peel_blocks = device_grid_blocks((const void*)k_peel, kT, 0);
+  int64_t initn = dg.n > L.pcap ? dg.n : L.pcap;
+  if (initn < 1) initn = 1;
+  hipLaunchKernelGGL(k_peel_init, dim3((unsigned)((initn + 255) / 256)), dim3(256), 0, s, L.ctl, dg.row_ptr, L.rlen,
+                     dg.n, dg.m, maxsr, force, L.pcap, L.pslot);
+  if (g_peel_blocks == 0) {
+    int dev = 0, cus = 0, occ = 0;
+    TRUSS_HIP(hipGetDevice(&dev));
+    TRUSS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    TRUSS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_peel, kT, 0));
+    if (occ < 1) {
+      set_last_error("peeling kernel does not fit on a compute unit");
+      return TRUSS_E_DEVICE;
+    }
+    g_peel_blocks = cus;  // one workgroup per compute unit
+  }
   int blocks = g_peel_blocks;
   if (opts && opts->grid_blocks > 0 && opts->grid_blocks < blocks) blocks = opts->grid_blocks;
   PeelArgs P;
@@ -610,24 +681,34 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
   P.ev = dg.ev;
   P.sr = sr;
   P.truss = truss_canon;
-  P.alist[0] = L.alist[0];
-  P.alist[1] = L.alist[1];
-  P.fq[0] = L.fq[0];
-  P.fq[1] = L.fq[1];
-  P.pe = L.pe;
-  P.pb = L.pb;
-  P.pj = L.pj;
-  P.pn = L.pn;
+  for (int i = 0; i < 2; ++i) {
+    P.alist[i] = L.alist[i];
+    P.fq[i] = L.fq[i];
+  }
+  P.pslot = L.pslot;
+  P.etab = dg.etab;
+  P.etab_mask = dg.etab_mask;
+  P.probe = (opts && opts->peel_probe == TRUSS_PROBE_BSEARCH) ? 1 : 0;
   P.ctl = L.ctl;
   void* args[] = {&P};
-  TRUSS_HIP(hipLaunchCooperativeKernel((const void*)k_peel, dim3(blocks), dim3(kT), args, 0, s));
   PeelCtl h;
-  TRUSS_HIP(hipMemcpyAsync(&h, L.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
-  TRUSS_HIP(hipStreamSynchronize(s));
+  int launches = 0;
+  for (;;) {
+    TRUSS_HIP(hipLaunchCooperativeKernel((const void*)k_peel, dim3(blocks), dim3(kT), args, 0, s));
+    ++launches;
+    TRUSS_HIP(hipMemcpyAsync(&h, L.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
+    TRUSS_HIP(hipStreamSynchronize(s));
+    if (h.abort || h.err || h.phase != PH_COMPACT) break;
+    hipLaunchKernelGGL(k_compact, dim3(2048), dim3(256), 0, s, dg.row_ptr, dg.col, dg.seid, L.rlen, dg.n, sr, L.ctl);
+  }
   res->kmax = h.kmax;
   res->levels = h.levels;
   res->subrounds = h.subrounds;
   res->work = (int64_t)h.w_work;
+  res->launches = launches;
+  res->heavy_rounds = h.heavy_rounds;
+  for (int b = 0; b < kHistBins; ++b) res->hist[b] = h.hist[b];
+  for (int b = 0; b < 6; ++b) res->phase_ms[b] = (double)h.t_phase[b] * 1e-5;
   if (h.abort) {
     set_last_error("peeling kernel barrier timed out");
     return TRUSS_E_INTERNAL;
@@ -635,6 +716,10 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
   if (h.err) {
     set_last_error("peeling exceeded the sub-round cap (%lld)", (long long)h.max_subrounds);
     return h.err;
+  }
+  if (h.phase != PH_DONE) {
+    set_last_error("peeling stopped in phase %d", h.phase);
+    return TRUSS_E_INTERNAL;
   }
   return TRUSS_OK;
 }

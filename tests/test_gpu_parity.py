@@ -17,7 +17,13 @@ from gpu_util import canonical_sorted, csr_graph, edges_graph, gpu_support, gpu_
 
 pytestmark = pytest.mark.gpu
 
-STRATS = [(1, 1), (2, 2), (3, 1), (1, 2), (2, 1)]  # (support strategy, peel mode)
+# option sets: support strategy (1 hash, 2 bsearch, 3 merge), frontier mode
+# (1 sparse, 2 dense), membership probe while peeling (1 hash table, 2 bsearch)
+STRATS = [dict(support_strategy=1, peel_mode=1, peel_probe=1),
+          dict(support_strategy=2, peel_mode=2, peel_probe=2),
+          dict(support_strategy=3, peel_mode=1, peel_probe=2),
+          dict(support_strategy=1, peel_mode=2, peel_probe=1),
+          dict(support_strategy=2, peel_mode=1, peel_probe=2)]
 
 
 def _both_formats(n, s, d, phi_ref, sup_ref=None, **opt):
@@ -42,8 +48,8 @@ def test_example2_fixture():
     n, s, d, phi_paper = golden_io.fig2()
     say("case: Example 2 fixture")
     sup_ref, _ = oracle.support_fwd(n, s, d)
-    for sup_s, mode in STRATS:
-        st = _both_formats(n, s, d, phi_paper, sup_ref, support_strategy=sup_s, peel_mode=mode)
+    for o in STRATS:
+        st = _both_formats(n, s, d, phi_paper, sup_ref, **o)
         assert st["kmax"] == 5
     got, _ = gpu_truss(edges_graph(n, s, d))
     np.testing.assert_array_equal(got, phi_paper)
@@ -56,8 +62,8 @@ def test_cliques(k):
     s, d = s.astype(np.int32), d.astype(np.int32)
     sup, tri = gpu_support(edges_graph(k, s, d))
     assert (sup == k - 2).all() and tri == k * (k - 1) * (k - 2) // 6
-    for sup_s, mode in STRATS:
-        got, st = gpu_truss(edges_graph(k, s, d), support_strategy=sup_s, peel_mode=mode)
+    for o in STRATS:
+        got, st = gpu_truss(edges_graph(k, s, d), **o)
         assert (got == k).all() and st["kmax"] == k
 
 
@@ -97,8 +103,7 @@ def test_random_small_graphs():
         say(f"case: ER trial {trial} n={n} m={s.size}")
         phi, _ = oracle.truss(n, s, d)
         sup, _ = oracle.support_fwd(n, s, d)
-        sup_s, mode = STRATS[trial % len(STRATS)]
-        _both_formats(n, s, d, phi, sup, support_strategy=sup_s, peel_mode=mode)
+        _both_formats(n, s, d, phi, sup, **STRATS[trial % len(STRATS)])
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
@@ -117,8 +122,8 @@ def test_rmat_vs_oracle(scale):
     say(f"case: R-MAT scale={scale} m={s.size}")
     phi, kmax = oracle.truss(n, s, d)
     sup, _ = oracle.support_fwd(n, s, d)
-    for sup_s, mode in STRATS[:3]:
-        st = _both_formats(n, s, d, phi, sup, support_strategy=sup_s, peel_mode=mode)
+    for o in STRATS[:3]:
+        st = _both_formats(n, s, d, phi, sup, **o)
         assert st["kmax"] == kmax
 
 
@@ -140,8 +145,9 @@ def test_heavy_walks_big_clique():
     s, d = s.astype(np.int32), d.astype(np.int32)
     g = csr_graph(k, s, d)
     for mode in (1, 2):
-        got, st = gpu_truss(g, peel_mode=mode)
-        assert (got == k).all() and st["kmax"] == k
+        for probe in (1, 2):
+            got, st = gpu_truss(g, peel_mode=mode, peel_probe=probe)
+            assert (got == k).all() and st["kmax"] == k
 
 
 def test_hub_graph_heavy_mixed():
@@ -175,8 +181,9 @@ def test_determinism_and_strategy_invariance():
         np.testing.assert_array_equal(got, ref)
     for sup_s in (1, 2, 3):
         for mode in (1, 2):
-            got, _ = gpu_truss(g, support_strategy=sup_s, peel_mode=mode)
-            np.testing.assert_array_equal(got, ref)
+            for probe in (1, 2):
+                got, _ = gpu_truss(g, support_strategy=sup_s, peel_mode=mode, peel_probe=probe)
+                np.testing.assert_array_equal(got, ref)
     T = lib()
     for sched in (T.SCHED_PLAIN, T.SCHED_HEURISTIC, T.SCHED_LEARNED):
         got, st = gpu_truss(g, scheduler=sched)
