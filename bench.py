@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--scheduler", default="heuristic", choices=["plain", "heuristic", "learned"])
+    ap.add_argument("--probe", default="auto", choices=["auto", "hash", "bsearch"])
+    ap.add_argument("--peel-mode", default="auto", choices=["auto", "sparse", "dense"])
+    ap.add_argument("--support", default="auto", choices=["auto", "hash", "bsearch", "merge"])
     ap.add_argument("--cpu-sample-scale", type=int, default=17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -108,7 +111,10 @@ def main():
         row_ptr, col = graphgen.to_csr(n, s, d)
         model = host_work_model(n, row_ptr, col)
     sched = {"plain": T.SCHED_PLAIN, "heuristic": T.SCHED_HEURISTIC, "learned": T.SCHED_LEARNED}[args.scheduler]
-    opts = T.make_options(scheduler=sched)
+    opts = T.make_options(scheduler=sched,
+                          peel_probe={"auto": 0, "hash": 1, "bsearch": 2}[args.probe],
+                          peel_mode={"auto": 0, "sparse": 1, "dense": 2}[args.peel_mode],
+                          support_strategy={"auto": 0, "hash": 1, "bsearch": 2, "merge": 3}[args.support])
     ws = T.workspace(g, opts)
     out = torch.empty(m, dtype=torch.int32, device="cuda:0")
     torch.cuda.synchronize()
@@ -153,7 +159,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "seed": args.seed,
-                   "n": n, "m": m, "scheduler": args.scheduler},
+                   "n": n, "m": m, "scheduler": args.scheduler, "probe": args.probe,
+                   "peel_mode": args.peel_mode, "support": args.support},
         "phases_ms": {"build": ms_build, "support": ms_sup, "peel": ms_peel},
         "kmax": st["kmax"], "levels": st["levels"], "subrounds": st["subrounds"],
         "triangles": st["triangles"], "peel_work": st["peel_work"], "launches": st["launches"],

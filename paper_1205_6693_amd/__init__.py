@@ -78,6 +78,9 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libtruss.so not built: run paper_1205_6693_amd/build.py "
                           "(or __graft_entry__.build())")
+    # torch ships its own HIP runtime; load it first so that libtruss binds to
+    # the same runtime (one process, one HIP runtime, shared streams and memory)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     gp = ctypes.POINTER(_Graph)

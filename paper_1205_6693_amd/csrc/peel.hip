@@ -46,8 +46,7 @@ namespace {
 
 constexpr int kT = 1024;
 constexpr int kWaves = kT / kWave;
-constexpr int kLight = 128;   // frontier edges with a longer walk are cut into pieces
-constexpr int kPiece = 512;   // adjacency entries per piece
+constexpr int kSeg = 4 * 1024;  // adjacency entries per segment of a chunk's walks
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kHistBins = 6;
 
@@ -115,7 +114,12 @@ struct PeelArgs {
   int32_t* truss;
   int32_t* alist[2];
   int32_t* fq[2];
-  unsigned long long* pslot;  // pieces: ((edge + 1) << 32) | piece index, 0 = empty
+  unsigned long long* pslot;  // segments: ((chunk start + 1) << 32) | segment index, 0 = empty
+  int32_t* rec_e;             // per frontier position: edge, search endpoint, row start, prefix
+  int32_t* rec_b;
+  int64_t* rec_base;
+  int32_t* rec_pre;
+  int32_t* rec_tot;           // per chunk of 64 positions: total walk length
   const EdgeSlot* etab;       // edge hash table
   unsigned long long etab_mask;
   int probe;                  // 0: hash table lookup, 1: binary search of the row
@@ -331,23 +335,89 @@ __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int3
   }
 }
 
-__device__ __forceinline__ void push_next(const PeelArgs& P, int32_t* q, int32_t f1, int32_t f2) {
-  const int p1 = wave_append(&P.ctl->w_qlen, f1 >= 0);
-  if (f1 >= 0) stc(&q[p1], f1);
-  const int p2 = wave_append(&P.ctl->w_qlen, f2 >= 0);
-  if (f2 >= 0) stc(&q[p2], f2);
+// Next-frontier edges are gathered per wavefront in LDS and appended to the
+// global queue 64 or more at a time, so the queue counter sees one atomic per
+// flush instead of one per wavefront iteration.
+constexpr int kWq = 192;  // capacity: a flush happens before 64 + 2 * 64 entries are exceeded
+struct WaveQueue {
+  int* buf;     // LDS, kWq entries, private to the wavefront
+  int cnt;      // wave-uniform fill level
+  int32_t* q;   // global next-frontier queue
+  int* count;   // its length
+};
+
+__device__ __forceinline__ void wq_flush(WaveQueue& wq) {
+  if (wq.cnt == 0) return;
+  wave_sync();
+  int base = 0;
+  if (lane_id() == 0) base = atomicAdd(wq.count, wq.cnt);
+  base = __shfl(base, 0, kWave);
+  for (int i = lane_id(); i < wq.cnt; i += kWave) stc(&wq.q[base + i], wq.buf[i]);
+  wq.cnt = 0;
+  wave_sync();
+}
+
+__device__ __forceinline__ void wq_push(WaveQueue& wq, int32_t f1, int32_t f2) {
+  const uint64_t m1 = ballot(f1 >= 0);
+  if (f1 >= 0) wq.buf[wq.cnt + rank_below(m1)] = f1;
+  wq.cnt += __popcll(m1);
+  const uint64_t m2 = ballot(f2 >= 0);
+  if (f2 >= 0) wq.buf[wq.cnt + rank_below(m2)] = f2;
+  wq.cnt += __popcll(m2);
+  if (wq.cnt >= kWave) wq_flush(wq);
+}
+
+// Block-wide append: every thread with `want` gets a distinct slot of the
+// global counter; one atomic per workgroup.  tmp: kWaves + 1 ints of LDS.
+__device__ __forceinline__ int block_append(int* counter, bool want, int* tmp) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const uint64_t m = ballot(want);
+  if (lane == 0) tmp[w] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int q = 0; q < kWaves; ++q) {
+      const int x = tmp[q];
+      tmp[q] = run;
+      run += x;
+    }
+    tmp[kWaves] = run ? atomicAdd(counter, run) : 0;
+  }
+  __syncthreads();
+  return tmp[kWaves] + tmp[w] + rank_below(m);
+}
+
+// Block-wide inclusive prefix sum of one int per thread; total in *total.
+__device__ __forceinline__ int block_inclusive_sum(int x, int* tmp, int* total) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const int inc = wave_inclusive_sum(x);
+  if (lane == kWave - 1) tmp[w] = inc;
+  __syncthreads();
+  int base = 0, all = 0;
+  for (int q = 0; q < kWaves; ++q) {
+    const int v = tmp[q];
+    if (q < w) base += v;
+    all += v;
+  }
+  *total = all;
+  __syncthreads();
+  return base + inc;
 }
 
 __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
-  __shared__ int s_pre[kWaves][kWave + 1];
-  __shared__ int s_e[kWaves][kWave];
-  __shared__ int s_b[kWaves][kWave];
-  __shared__ int64_t s_base[kWaves][kWave];
+  __shared__ int s_pre[kT + 1];
+  __shared__ int s_e[kT];
+  __shared__ int s_b[kT];
+  __shared__ int64_t s_base[kT];
+  __shared__ int s_wq[kWaves][kWq];
+  __shared__ int s_tmp[kWaves + 2];
+  __shared__ int s_c0;
+  __shared__ unsigned long long s_pv;
+  __shared__ int s_inl;
   PeelCtl* c = P.ctl;
+  const int tid = threadIdx.x;
   const int lane = lane_id();
-  const int wv = threadIdx.x / kWave;
-  const int64_t gwave = (blockIdx.x * (int64_t)kT + threadIdx.x) / kWave;
-  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  const int wv = tid / kWave;
   unsigned long long my_work = 0;
 
   for (;;) {
@@ -364,17 +434,17 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       const int32_t* A = P.alist[acur];
       int32_t* B = P.alist[acur ^ 1];
       int mins = kIntMax;
-      for (int64_t base = gwave * kWave; base < cnt; base += nwaves * kWave) {
-        const int64_t i = base + lane;
+      for (int64_t base = (int64_t)blockIdx.x * kT; base < cnt; base += (int64_t)gridDim.x * kT) {
+        const int64_t i = base + tid;
         bool live = false;
         int32_t e = 0;
         if (i < cnt) {
           e = first ? (int32_t)i : ldc(&A[i]);
-          const int2 s = ldc2(&P.sr[e]);
-          live = s.y == 0;
-          if (live && s.x < mins) mins = s.x;
+          const int2 sv = ldc2(&P.sr[e]);
+          live = sv.y == 0;
+          if (live && sv.x < mins) mins = sv.x;
         }
-        const int pos = wave_append(&c->w_alive, live);
+        const int pos = block_append(&c->w_alive, live, s_tmp);
         if (live) stc(&B[pos], e);
       }
       mins = wave_min(mins);
@@ -385,40 +455,58 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       const int32_t* A = P.alist[acur];
       const int stamp = phase == PH_START ? r : r + 1;
       int32_t* Q = P.fq[stamp & 1];
-      for (int64_t base = gwave * kWave; base < cnt; base += nwaves * kWave) {
-        const int64_t i = base + lane;
+      for (int64_t base = (int64_t)blockIdx.x * kT; base < cnt; base += (int64_t)gridDim.x * kT) {
+        const int64_t i = base + tid;
         bool take = false;
         int32_t e = 0;
         if (i < cnt) {
           e = ldc(&A[i]);
-          const int2 s = ldc2(&P.sr[e]);
-          take = s.y == 0 && s.x <= l;
+          const int2 sv = ldc2(&P.sr[e]);
+          take = sv.y == 0 && sv.x <= l;
           if (take) {
             stc_stamp(&P.sr[e], stamp);
             P.truss[e] = k;
           }
         }
-        const int pos = wave_append(&c->w_qlen, take);
+        const int pos = block_append(&c->w_qlen, take, s_tmp);
         if (take) stc(&Q[pos], e);
       }
     } else if (phase == PH_PROC) {
       const int qn = ldc(&c->qlen);
       const bool sparse = ldc(&c->mode) == TRUSS_PEEL_SPARSE;
       const int32_t* Q = P.fq[r & 1];
-      int32_t* Qn = P.fq[(r + 1) & 1];
+      WaveQueue wq{s_wq[wv], 0, P.fq[(r + 1) & 1], &c->w_qlen};
       const unsigned long long cap = (unsigned long long)ldc(&c->pcap);
-      // (1) frontier edges in chunks of 64: short walks flattened across the
-      // wave, long walks cut into pieces that any wave may take
+      // walk items [lo, hi) of the chunk held in the workgroup's LDS tables
+      auto walk = [&](int lo, int hi) {
+        for (int t0 = lo; t0 < hi; t0 += kT) {
+          const int t = t0 + tid;
+          int32_t f1 = -1, f2 = -1;
+          if (t < hi) {
+            int x = 0, y = kT - 1;  // last edge whose range starts at or before t
+            while (x < y) {
+              const int mid = (x + y + 1) >> 1;
+              if (s_pre[mid] <= t) x = mid; else y = mid - 1;
+            }
+            process_entry(P, s_e[x], s_b[x], s_base[x] + (t - s_pre[x]), r, l, k, sparse, f1, f2);
+          }
+          wq_push(wq, f1, f2);
+        }
+        if (tid == 0) my_work += (unsigned long long)(hi - lo);
+      };
+      // (1) frontier edges in chunks of kT, one edge a thread.  The walks of a
+      // chunk are laid end to end and cut into segments of kSeg entries; the
+      // workgroup walks segment 0 and announces the others, which any
+      // workgroup may take.
       for (;;) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&c->w_fetch, kWave);
-        base = __shfl(base, 0, kWave);
-        if (base >= qn) break;
-        const int i = base + lane;
-        const bool valid = i < qn;
+        if (tid == 0) s_c0 = atomicAdd(&c->w_fetch, kT);
+        __syncthreads();
+        const int c0 = s_c0;
+        if (c0 >= qn) break;
+        const int i = c0 + tid;
         int32_t e = 0, a = 0, b = 0;
         int work = 0;
-        if (valid) {
+        if (i < qn) {
           e = ldc(&Q[i]);
           const int32_t u = P.eu[e], v = P.ev[e];
           const int du = P.rlen[u], dv = P.rlen[v];
@@ -428,112 +516,88 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
           work = ua ? du : dv;
         }
         const int64_t ra = P.row_ptr[a];
-        const bool heavy = work > kLight;
-        if (ballot(heavy)) {
-          int64_t inl_lo = 0, inl_hi = 0;
-          const int np = heavy ? (work + kPiece - 1) / kPiece : 0;
-          const int pinc = wave_inclusive_sum(np);
-          const int ptot = __shfl(pinc, kWave - 1, kWave);
-          unsigned long long pbase = 0;
-          if (lane == 0) pbase = atomicAdd(&c->w_pieces, (unsigned long long)ptot);
-          pbase = __shfl(pbase, 0, kWave);
-          if (heavy) {
-            const unsigned long long first = pbase + (unsigned long long)(pinc - np);
-            for (int q = 0; q < np; ++q) {
-              const unsigned long long slot = first + (unsigned long long)q;
-              if (slot < cap) {
-                stc(&P.pslot[slot], ((unsigned long long)(e + 1) << 32) | (unsigned)q);
-              } else {
-                const int64_t j0 = ra + (int64_t)q * kPiece;
-                const int len = work - q * kPiece < kPiece ? work - q * kPiece : kPiece;
-                if (inl_hi == 0) inl_lo = j0;
-                inl_hi = j0 + len;
-              }
-            }
+        int W = 0;
+        const int inc = block_inclusive_sum(work, s_tmp, &W);
+        s_pre[tid + 1] = inc;
+        if (tid == 0) s_pre[0] = 0;
+        s_e[tid] = e;
+        s_b[tid] = b;
+        s_base[tid] = ra;
+        const int nseg = (W + kSeg - 1) / kSeg;
+        if (nseg > 1) {
+          // chunk tables for other workgroups, then the segment announcements
+          stc(&P.rec_e[i], e);
+          stc(&P.rec_b[i], b);
+          stc(&P.rec_base[i], ra);
+          stc(&P.rec_pre[i], inc - work);
+          if (tid == 0) stc(&P.rec_tot[c0 / kT], W);
+          mem_wait();
+          __syncthreads();
+          if (tid == 0) {
+            const unsigned long long pbase = atomicAdd(&c->w_pieces, (unsigned long long)(nseg - 1));
+            const unsigned long long room = pbase < cap ? cap - pbase : 0ULL;
+            s_inl = room < (unsigned long long)(nseg - 1) ? 1 + (int)room : nseg;
+            s_pv = pbase;
           }
-          work = heavy ? 0 : work;
-          // pieces that found no slot: this wave walks them, one edge at a time
-          uint64_t om = ballot(inl_hi > inl_lo);
-          while (om) {
-            const int src = __builtin_ctzll(om);
-            om &= om - 1;
-            const int32_t oe = __shfl(e, src, kWave), ob = __shfl(b, src, kWave);
-            const int64_t lo = __shfl(inl_lo, src, kWave), hi = __shfl(inl_hi, src, kWave);
-            for (int64_t j0 = lo; j0 < hi; j0 += kWave) {
-              int32_t f1 = -1, f2 = -1;
-              if (j0 + lane < hi) process_entry(P, oe, ob, j0 + lane, r, l, k, sparse, f1, f2);
-              push_next(P, Qn, f1, f2);
-            }
-            if (lane == 0) my_work += (unsigned long long)(hi - lo);
+          __syncthreads();
+          const unsigned long long pbase = s_pv;
+          for (int sg = 1 + tid; sg < nseg; sg += kT) {
+            const unsigned long long slot = pbase + (unsigned long long)(sg - 1);
+            if (slot < cap) stc(&P.pslot[slot], ((unsigned long long)(c0 + 1) << 32) | (unsigned)sg);
           }
+        } else if (tid == 0) {
+          s_inl = nseg;
         }
-        const int inc = wave_inclusive_sum(work);
-        const int W = __shfl(inc, kWave - 1, kWave);
-        s_pre[wv][lane + 1] = inc;
-        if (lane == 0) s_pre[wv][0] = 0;
-        s_e[wv][lane] = e;
-        s_b[wv][lane] = b;
-        s_base[wv][lane] = ra;
-        wave_sync();
-        if (lane == 0) my_work += (unsigned long long)W;
-        for (int t0 = 0; t0 < W; t0 += kWave) {
-          const int t = t0 + lane;
-          int32_t f1 = -1, f2 = -1;
-          if (t < W) {
-            int lo = 0, hi = kWave - 1;  // last lane whose range starts at or before t
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (s_pre[wv][mid] <= t) lo = mid; else hi = mid - 1;
-            }
-            process_entry(P, s_e[wv][lo], s_b[wv][lo], s_base[wv][lo] + (t - s_pre[wv][lo]), r, l, k, sparse, f1,
-                          f2);
-          }
-          push_next(P, Qn, f1, f2);
-        }
-        wave_sync();
+        __syncthreads();
+        const int inl_from = s_inl;
+        walk(0, W < kSeg ? W : kSeg);
+        for (int sg = inl_from; sg < nseg; ++sg) walk(sg * kSeg, (sg + 1) * kSeg < W ? (sg + 1) * kSeg : W);
+        __syncthreads();
       }
-      // (2) pieces: every wave takes pieces until all waves are done with (1)
-      // and every claimed piece has been taken.  A piece is published by a
-      // single 64-bit store and cleared by the wave that takes it.
+      // (2) announced segments: every workgroup takes segments until all
+      // workgroups are done with (1) and every announced segment has been
+      // taken.  A segment is announced by one 64-bit store and cleared by the
+      // workgroup that takes it.
       mem_wait();
-      if (lane == 0) atomicAdd(&c->w_lightdone, 1);
+      __syncthreads();
+      if (tid == 0) atomicAdd(&c->w_lightdone, 1);
       for (;;) {
-        int q = 0;
-        if (lane == 0) q = atomicAdd(&c->w_pfetch, 1);
-        q = __shfl(q, 0, kWave);
-        unsigned long long pv = 0;
-        for (;;) {
-          if ((unsigned long long)q < cap) pv = ldc(&P.pslot[q]);
-          if (pv != 0) break;
-          const unsigned long long claimed = ldc(&c->w_pieces);
-          const unsigned long long limit = claimed < cap ? claimed : cap;
-          if (ldc(&c->w_lightdone) == (int)nwaves && (unsigned long long)q >= limit) break;
-          __builtin_amdgcn_s_sleep(1);
+        if (tid == 0) {
+          const int q = atomicAdd(&c->w_pfetch, 1);
+          unsigned long long pv = 0;
+          for (;;) {
+            if ((unsigned long long)q < cap) pv = ldc(&P.pslot[q]);
+            if (pv != 0) break;
+            const unsigned long long claimed = ldc(&c->w_pieces);
+            const unsigned long long limit = claimed < cap ? claimed : cap;
+            if (ldc(&c->w_lightdone) == (int)gridDim.x && (unsigned long long)q >= limit) break;
+            __builtin_amdgcn_s_sleep(1);
+          }
+          if (pv != 0) stc(&P.pslot[q], 0ULL);
+          s_pv = pv;
         }
-        pv = __shfl(pv, 0, kWave);
+        __syncthreads();
+        const unsigned long long pv = s_pv;
         if (pv == 0) break;
-        if (lane == 0) stc(&P.pslot[q], 0ULL);
-        const int32_t e = (int32_t)(pv >> 32) - 1;
-        const int qi = (int)(pv & 0xffffffffu);
-        const int32_t u = P.eu[e], v = P.ev[e];
-        const int du = P.rlen[u], dv = P.rlen[v];
-        const bool ua = du < dv || (du == dv && u < v);
-        const int32_t a = ua ? u : v, b = ua ? v : u;
-        const int work = ua ? du : dv;
-        const int64_t j0 = P.row_ptr[a] + (int64_t)qi * kPiece;
-        const int len = work - qi * kPiece < kPiece ? work - qi * kPiece : kPiece;
-        for (int t0 = 0; t0 < len; t0 += kWave) {
-          int32_t f1 = -1, f2 = -1;
-          if (t0 + lane < len) process_entry(P, e, b, j0 + t0 + lane, r, l, k, sparse, f1, f2);
-          push_next(P, Qn, f1, f2);
-        }
-        if (lane == 0) my_work += (unsigned long long)len;
+        const int c0 = (int)(pv >> 32) - 1;
+        const int sg = (int)(pv & 0xffffffffu);
+        const int i = c0 + tid;
+        const bool ok = i < qn;
+        s_pre[tid] = ok ? ldc(&P.rec_pre[i]) : kIntMax;
+        s_e[tid] = ok ? ldc(&P.rec_e[i]) : 0;
+        s_b[tid] = ok ? ldc(&P.rec_b[i]) : 0;
+        s_base[tid] = ok ? ldc(&P.rec_base[i]) : 0;
+        const int W = ldc(&P.rec_tot[c0 / kT]);
+        if (tid == 0) s_pre[kT] = W;
+        __syncthreads();
+        walk(sg * kSeg, (sg + 1) * kSeg < W ? (sg + 1) * kSeg : W);
+        __syncthreads();
       }
+      wq_flush(wq);
     }
     if (!phase_barrier(c)) break;
   }
-  my_work = wave_sum(my_work);
-  if (lane == 0 && my_work) atomicAdd(&c->w_work, my_work);
+  if (tid == 0 && my_work) atomicAdd(&c->w_work, my_work);
 }
 
 // Stable in-place compaction of every row to its live entries (a wavefront a row).
@@ -621,6 +685,8 @@ struct PeelLayout {
   int32_t* alist[2];
   int32_t* fq[2];
   unsigned long long* pslot;
+  int32_t *rec_e, *rec_b, *rec_pre, *rec_tot;
+  int64_t* rec_base;
   int pcap;
 };
 
@@ -632,6 +698,11 @@ void carve(const DevGraph& dg, Arena& a, PeelLayout& L) {
   for (int i = 0; i < 2; ++i) L.fq[i] = a.take<int32_t>(m + 1);
   L.pcap = (int)(m < (1 << 22) ? m : (1 << 22));
   L.pslot = a.take<unsigned long long>(L.pcap + 1);
+  L.rec_e = a.take<int32_t>(m + kT);
+  L.rec_b = a.take<int32_t>(m + kT);
+  L.rec_pre = a.take<int32_t>(m + kT);
+  L.rec_base = a.take<int64_t>(m + kT);
+  L.rec_tot = a.take<int32_t>(m / kT + 2);
 }
 
 int g_peel_blocks = 0;
@@ -686,6 +757,11 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
     P.fq[i] = L.fq[i];
   }
   P.pslot = L.pslot;
+  P.rec_e = L.rec_e;
+  P.rec_b = L.rec_b;
+  P.rec_pre = L.rec_pre;
+  P.rec_base = L.rec_base;
+  P.rec_tot = L.rec_tot;
   P.etab = dg.etab;
   P.etab_mask = dg.etab_mask;
   P.probe = (opts && opts->peel_probe == TRUSS_PROBE_BSEARCH) ? 1 : 0;
