@@ -60,21 +60,25 @@ enum Phase : int {
   PH_DONE = 6
 };
 
+constexpr int kGroups = 8;  // barrier arrival groups (workgroup id mod 8: one per XCD under round-robin dispatch)
+
 struct alignas(256) PeelCtl {
-  unsigned bar_count;
+  unsigned bar_count;          // groups arrived
   unsigned pad0[63];
   unsigned bar_gen;
   unsigned pad1[63];
-  // working counters, reset by the control step
-  int w_fetch;
-  int w_qlen;
-  int w_alive;
-  int w_minsup;
-  int w_pfetch;
-  int w_lightdone;  // waves that finished their own frontier edges this round
-  unsigned long long w_pieces;  // pieces appended this round (may exceed capacity)
-  unsigned long long w_work;
-  int pad3[54];
+  unsigned grp_count[kGroups][32];  // workgroups arrived, per group (one 128-byte line each)
+  // working counters, reset by the control step; each on its own 128-byte
+  // line so that polling one does not slow the atomics on another
+  alignas(128) int w_fetch;               // frontier chunk fetch
+  alignas(128) int w_qlen;                // next-frontier queue length
+  alignas(128) int w_alive;               // live-list length
+  alignas(128) int w_minsup;              // minimum live support
+  alignas(128) unsigned long long w_pfetch;  // segment indices drawn
+  alignas(128) int w_chunks;              // frontier chunks finished
+  alignas(128) unsigned long long w_pieces;  // segments announced (may exceed the slot capacity)
+  alignas(128) unsigned long long w_work;
+  alignas(128) int pad3;
   // published control state, written only by the control step
   int phase;
   int k;
@@ -114,7 +118,7 @@ struct PeelArgs {
   int32_t* truss;
   int32_t* alist[2];
   int32_t* fq[2];
-  unsigned long long* pslot;  // segments: ((chunk start + 1) << 32) | segment index, 0 = empty
+  unsigned long long* pslot;  // segment slots: 0 = free, ((chunk start + 1) << 32) | segment = announced
   int32_t* rec_e;             // per frontier position: edge, search endpoint, row start, prefix
   int32_t* rec_b;
   int64_t* rec_base;
@@ -229,8 +233,8 @@ __device__ void control_step(PeelCtl* c) {
     case PH_PROC: {
       if (ldc(&c->w_pieces) != 0ULL) stc(&c->heavy_rounds, ldc(&c->heavy_rounds) + 1);
       stc(&c->w_pieces, 0ULL);
-      stc(&c->w_pfetch, 0);
-      stc(&c->w_lightdone, 0);
+      stc(&c->w_pfetch, 0ULL);
+      stc(&c->w_chunks, 0);
       if (ldc(&c->mode) == TRUSS_PEEL_DENSE) {
         stc(&c->w_qlen, 0);
         stc(&c->w_fetch, 0);
@@ -263,8 +267,19 @@ __device__ bool phase_barrier(PeelCtl* c) {
   if (threadIdx.x == 0) {
     int ok = 1;
     const unsigned gen = ldc(&c->bar_gen);
-    const unsigned prev = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == gridDim.x - 1) {
+    // two-level arrival: the last workgroup of a group arrives for the group
+    const unsigned g = blockIdx.x % kGroups;
+    const unsigned gsize = (gridDim.x - g + kGroups - 1) / kGroups;
+    const unsigned ngroups = gridDim.x < (unsigned)kGroups ? gridDim.x : (unsigned)kGroups;
+    bool last = false;
+    const unsigned pg = __hip_atomic_fetch_add(&c->grp_count[g][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (pg == gsize - 1) {
+      stc(&c->grp_count[g][0], 0u);
+      mem_wait();
+      const unsigned prev = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = prev == ngroups - 1;
+    }
+    if (last) {
       control_step(c);
       stc(&c->bar_count, 0u);
       mem_wait();
@@ -477,6 +492,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       const int32_t* Q = P.fq[r & 1];
       WaveQueue wq{s_wq[wv], 0, P.fq[(r + 1) & 1], &c->w_qlen};
       const unsigned long long cap = (unsigned long long)ldc(&c->pcap);
+      unsigned long long* slots = P.pslot;
       // walk items [lo, hi) of the chunk held in the workgroup's LDS tables
       auto walk = [&](int lo, int hi) {
         for (int t0 = lo; t0 < hi; t0 += kT) {
@@ -494,12 +510,15 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         }
         if (tid == 0) my_work += (unsigned long long)(hi - lo);
       };
-      // (1) frontier edges in chunks of kT, one edge a thread.  The walks of a
+      // (1) frontier edges in chunks of kT, one edge a thread (the first chunk
+      // of every workgroup is static, the rest are fetched).  The walks of a
       // chunk are laid end to end and cut into segments of kSeg entries; the
-      // workgroup walks segment 0 and announces the others, which any
-      // workgroup may take.
+      // workgroup walks segment 0 and announces the others for any workgroup
+      // to take.  A segment is announced by one 64-bit store into a slot.
+      bool first_chunk = true;
       for (;;) {
-        if (tid == 0) s_c0 = atomicAdd(&c->w_fetch, kT);
+        if (tid == 0) s_c0 = first_chunk ? (int)blockIdx.x * kT : (int)gridDim.x * kT + atomicAdd(&c->w_fetch, kT);
+        first_chunk = false;
         __syncthreads();
         const int c0 = s_c0;
         if (c0 >= qn) break;
@@ -524,6 +543,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         s_b[tid] = b;
         s_base[tid] = ra;
         const int nseg = (W + kSeg - 1) / kSeg;
+        int npub = 0;  // segments 1..npub are announced
         if (nseg > 1) {
           // chunk tables for other workgroups, then the segment announcements
           stc(&P.rec_e[i], e);
@@ -533,52 +553,86 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
           if (tid == 0) stc(&P.rec_tot[c0 / kT], W);
           mem_wait();
           __syncthreads();
-          if (tid == 0) {
-            const unsigned long long pbase = atomicAdd(&c->w_pieces, (unsigned long long)(nseg - 1));
-            const unsigned long long room = pbase < cap ? cap - pbase : 0ULL;
-            s_inl = room < (unsigned long long)(nseg - 1) ? 1 + (int)room : nseg;
-            s_pv = pbase;
-          }
+          if (tid == 0) s_pv = atomicAdd(&c->w_pieces, (unsigned long long)(nseg - 1));
           __syncthreads();
           const unsigned long long pbase = s_pv;
-          for (int sg = 1 + tid; sg < nseg; sg += kT) {
-            const unsigned long long slot = pbase + (unsigned long long)(sg - 1);
-            if (slot < cap) stc(&P.pslot[slot], ((unsigned long long)(c0 + 1) << 32) | (unsigned)sg);
-          }
-        } else if (tid == 0) {
-          s_inl = nseg;
+          const unsigned long long room = pbase < cap ? cap - pbase : 0ULL;
+          npub = room < (unsigned long long)(nseg - 1) ? (int)room : nseg - 1;
+          const unsigned long long code0 = (unsigned long long)(c0 + 1) << 32;
+          for (int sg = 1 + tid; sg <= npub; sg += kT)
+            stc(&slots[pbase + (unsigned long long)(sg - 1)], code0 | (unsigned)sg);
         }
         __syncthreads();
-        const int inl_from = s_inl;
         walk(0, W < kSeg ? W : kSeg);
-        for (int sg = inl_from; sg < nseg; ++sg) walk(sg * kSeg, (sg + 1) * kSeg < W ? (sg + 1) * kSeg : W);
+        // segments that found no slot
+        for (int sg = npub + 1; sg < nseg; ++sg) walk(sg * kSeg, (sg + 1) * kSeg < W ? (sg + 1) * kSeg : W);
+        if (tid == 0) atomicAdd(&c->w_chunks, 1);
         __syncthreads();
       }
-      // (2) announced segments: every workgroup takes segments until all
-      // workgroups are done with (1) and every announced segment has been
-      // taken.  A segment is announced by one 64-bit store and cleared by the
-      // workgroup that takes it.
-      mem_wait();
-      __syncthreads();
-      if (tid == 0) atomicAdd(&c->w_lightdone, 1);
+      // (2) take announced segments.  A workgroup draws one index of the
+      // announcement order at a time and keeps it until that slot is
+      // announced (then takes and clears it) or until every chunk is finished
+      // with fewer announcements than the index (then stops).  Indices are
+      // drawn in order and never dropped, so each announced slot is taken
+      // exactly once.
+      const int nchunks = (qn + kT - 1) / kT;
       for (;;) {
         if (tid == 0) {
-          const int q = atomicAdd(&c->w_pfetch, 1);
-          unsigned long long pv = 0;
+          unsigned long long pv = ~0ULL;
+          // nothing announced and nothing left to announce: skip the draw
+          bool draw = true;
+          const uint64_t t0 = wall_clock64();
           for (;;) {
-            if ((unsigned long long)q < cap) pv = ldc(&P.pslot[q]);
-            if (pv != 0) break;
-            const unsigned long long claimed = ldc(&c->w_pieces);
-            const unsigned long long limit = claimed < cap ? claimed : cap;
-            if (ldc(&c->w_lightdone) == (int)gridDim.x && (unsigned long long)q >= limit) break;
-            __builtin_amdgcn_s_sleep(1);
+            if (ldc(&c->w_chunks) >= nchunks && ldc(&c->w_pieces) == 0ULL) {
+              draw = false;
+              break;
+            }
+            if (ldc(&c->w_pieces) != 0ULL) break;
+            __builtin_amdgcn_s_sleep(2);
+            if (wall_clock64() - t0 > 3000000000ULL) {  // 30 s: give up, wind down
+              stc(&c->abort, 1);
+              draw = false;
+              break;
+            }
           }
-          if (pv != 0) stc(&P.pslot[q], 0ULL);
+          if (draw) {
+            const unsigned long long q = atomicAdd(&c->w_pfetch, 1ULL);
+            for (;;) {
+              const unsigned long long cl = ldc(&c->w_pieces);
+              const unsigned long long limit = cl < cap ? cl : cap;
+              if (q < limit) {
+                // the owner announces right after claiming the slot range
+                unsigned long long v;
+                while ((v = ldc(&slots[q])) == 0ULL) {
+                  __builtin_amdgcn_s_sleep(1);
+                  if (wall_clock64() - t0 > 3000000000ULL) break;
+                }
+                if (v == 0ULL) {
+                  stc(&c->abort, 1);
+                  break;
+                }
+                stc(&slots[q], 0ULL);
+                pv = v;
+                break;
+              }
+              if (ldc(&c->w_chunks) >= nchunks) {
+                const unsigned long long cl2 = ldc(&c->w_pieces);
+                if (q >= (cl2 < cap ? cl2 : cap)) break;  // final count reached: stop
+                continue;
+              }
+              __builtin_amdgcn_s_sleep(2);
+              if (wall_clock64() - t0 > 3000000000ULL) {  // 30 s: give up, wind down
+                stc(&c->abort, 1);
+                break;
+              }
+            }
+          }
           s_pv = pv;
         }
         __syncthreads();
         const unsigned long long pv = s_pv;
-        if (pv == 0) break;
+        __syncthreads();
+        if (pv == ~0ULL) break;
         const int c0 = (int)(pv >> 32) - 1;
         const int sg = (int)(pv & 0xffffffffu);
         const int i = c0 + tid;
@@ -645,12 +699,13 @@ __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int
   if (i == 0) {
     c->bar_count = 0;
     c->bar_gen = 0;
+    for (int g = 0; g < kGroups; ++g) c->grp_count[g][0] = 0;
     c->w_fetch = 0;
     c->w_qlen = 0;
     c->w_alive = 0;
     c->w_minsup = kIntMax;
-    c->w_pfetch = 0;
-    c->w_lightdone = 0;
+    c->w_pfetch = 0ULL;
+    c->w_chunks = 0;
     c->w_pieces = 0ULL;
     c->w_work = 0ULL;
     c->phase = PH_SWEEP;
