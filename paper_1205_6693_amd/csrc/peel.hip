@@ -155,39 +155,49 @@ __device__ __forceinline__ int hist_bin(long long q) {
 }
 
 // ---- control step: one thread of the last workgroup to reach a barrier -----------------------
+// All inputs are loaded first (independent loads in flight together), the
+// decision is made in registers, and the outputs are stored at the end.
 __device__ void control_step(PeelCtl* c) {
   int phase = ldc(&c->phase);
-  {
-    const unsigned long long now = wall_clock64();
-    const unsigned long long last = ldc(&c->t_last);
-    if (last != 0 && phase >= 0 && phase < 8) stc(&c->t_phase[phase], ldc(&c->t_phase[phase]) + (now - last));
-    stc(&c->t_last, now);
-  }
-  const int r = ldc(&c->r);
+  int k = ldc(&c->k);
+  int r = ldc(&c->r);
+  int acnt = ldc(&c->acnt);
+  int acur = ldc(&c->acur);
+  const int mode_in = ldc(&c->mode);
+  const int force = ldc(&c->force_mode);
+  int levels = ldc(&c->levels);
+  long long removed_level = ldc(&c->removed_level);
+  long long csr_live = ldc(&c->csr_live);
   long long subrounds = ldc(&c->subrounds);
+  long long heavy_rounds = ldc(&c->heavy_rounds);
   const long long maxsr = ldc(&c->max_subrounds);
+  const unsigned long long t_last = ldc(&c->t_last);
+  const int w_qlen = ldc(&c->w_qlen);
+  const int w_alive = ldc(&c->w_alive);
+  const int w_minsup = ldc(&c->w_minsup);
+  const unsigned long long w_pieces = ldc(&c->w_pieces);
+  const int phase_in = phase;
+  const unsigned long long now = wall_clock64();
+  int qlen_out = -1, mode_out = -1, first_out = -1, hist_bin_out = -1;
+  bool reset_sweep = false, reset_queue = false, reset_proc = false;
+
   auto begin_round = [&](int q) {
-    stc(&c->qlen, q);
+    qlen_out = q;
     subrounds += 1;
-    stc(&c->subrounds, subrounds);
-    const int b = hist_bin(q);
-    stc(&c->hist[b], ldc(&c->hist[b]) + 1);
+    hist_bin_out = hist_bin(q);
     phase = PH_PROC;
   };
   auto next_round = [&]() {
-    const int q = ldc(&c->w_qlen);
-    stc(&c->w_qlen, 0);
-    stc(&c->w_fetch, 0);
-    if (q > 0) {
-      stc(&c->r, r + 1);
-      stc(&c->removed_level, ldc(&c->removed_level) + q);
-      begin_round(q);
+    reset_queue = true;
+    if (w_qlen > 0) {
+      r += 1;
+      removed_level += w_qlen;
+      begin_round(w_qlen);
     } else {
       // level finished: compact the rows when the live count has halved
-      const long long alive_after = (long long)ldc(&c->acnt) - ldc(&c->removed_level);
-      const long long live = ldc(&c->csr_live);
-      if (alive_after > 0 && alive_after * 2 < live) {
-        stc(&c->csr_live, alive_after);
+      const long long alive_after = (long long)acnt - removed_level;
+      if (alive_after > 0 && alive_after * 2 < csr_live) {
+        csr_live = alive_after;
         phase = PH_COMPACT;
       } else {
         phase = PH_SWEEP;
@@ -195,55 +205,39 @@ __device__ void control_step(PeelCtl* c) {
     }
   };
   switch (phase) {
-    case PH_SWEEP: {
-      const int alive = ldc(&c->w_alive);
-      const int minsup = ldc(&c->w_minsup);
-      stc(&c->w_alive, 0);
-      stc(&c->w_minsup, kIntMax);
-      stc(&c->acnt, alive);
-      stc(&c->acur, ldc(&c->acur) ^ 1);
-      stc(&c->first, 0);
-      if (alive == 0) {
+    case PH_SWEEP:
+      reset_sweep = true;
+      acnt = w_alive;
+      acur ^= 1;
+      first_out = 0;
+      if (w_alive == 0) {
         phase = PH_DONE;
         break;
       }
-      int k = ldc(&c->k) + 1;
-      if (minsup + 2 > k) k = minsup + 2;
-      stc(&c->k, k);
-      stc(&c->kmax, k);
-      stc(&c->levels, ldc(&c->levels) + 1);
-      stc(&c->r, r + 1);
-      stc(&c->removed_level, 0LL);
-      const int fm = ldc(&c->force_mode);
-      stc(&c->mode, fm == TRUSS_PEEL_DENSE ? (int)TRUSS_PEEL_DENSE : (int)TRUSS_PEEL_SPARSE);
-      stc(&c->w_qlen, 0);
-      stc(&c->w_fetch, 0);
+      k = (w_minsup + 2 > k + 1) ? w_minsup + 2 : k + 1;
+      levels += 1;
+      r += 1;
+      removed_level = 0;
+      mode_out = force == TRUSS_PEEL_DENSE ? (int)TRUSS_PEEL_DENSE : (int)TRUSS_PEEL_SPARSE;
+      reset_queue = true;
       phase = PH_START;
       break;
-    }
-    case PH_START: {
-      const int q = ldc(&c->w_qlen);
-      stc(&c->w_qlen, 0);
-      stc(&c->w_fetch, 0);
-      stc(&c->removed_level, (long long)q);
-      if (q > 0) begin_round(q);
+    case PH_START:
+      reset_queue = true;
+      removed_level = w_qlen;
+      if (w_qlen > 0) begin_round(w_qlen);
       else phase = PH_SWEEP;
       break;
-    }
-    case PH_PROC: {
-      if (ldc(&c->w_pieces) != 0ULL) stc(&c->heavy_rounds, ldc(&c->heavy_rounds) + 1);
-      stc(&c->w_pieces, 0ULL);
-      stc(&c->w_pfetch, 0ULL);
-      stc(&c->w_chunks, 0);
-      if (ldc(&c->mode) == TRUSS_PEEL_DENSE) {
-        stc(&c->w_qlen, 0);
-        stc(&c->w_fetch, 0);
+    case PH_PROC:
+      reset_proc = true;
+      if (w_pieces != 0ULL) heavy_rounds += 1;
+      if (mode_in == TRUSS_PEEL_DENSE) {
+        reset_queue = true;
         phase = PH_DENSE;
         break;
       }
       next_round();
       break;
-    }
     case PH_DENSE:
       next_round();
       break;
@@ -254,6 +248,37 @@ __device__ void control_step(PeelCtl* c) {
     stc(&c->err, (int)TRUSS_E_INTERNAL);
     phase = PH_DONE;
   }
+  // outputs
+  if (t_last != 0 && phase_in >= 0 && phase_in < 8)
+    stc(&c->t_phase[phase_in], ldc(&c->t_phase[phase_in]) + (now - t_last));
+  stc(&c->t_last, now);
+  if (hist_bin_out >= 0) stc(&c->hist[hist_bin_out], ldc(&c->hist[hist_bin_out]) + 1);
+  if (reset_sweep) {
+    stc(&c->w_alive, 0);
+    stc(&c->w_minsup, kIntMax);
+  }
+  if (reset_queue) {
+    stc(&c->w_qlen, 0);
+    stc(&c->w_fetch, 0);
+  }
+  if (reset_proc) {
+    stc(&c->w_pieces, 0ULL);
+    stc(&c->w_pfetch, 0ULL);
+    stc(&c->w_chunks, 0);
+  }
+  if (qlen_out >= 0) stc(&c->qlen, qlen_out);
+  if (mode_out >= 0) stc(&c->mode, mode_out);
+  if (first_out >= 0) stc(&c->first, first_out);
+  stc(&c->k, k);
+  stc(&c->kmax, k);
+  stc(&c->r, r);
+  stc(&c->acnt, acnt);
+  stc(&c->acur, acur);
+  stc(&c->levels, levels);
+  stc(&c->removed_level, removed_level);
+  stc(&c->csr_live, csr_live);
+  stc(&c->subrounds, subrounds);
+  stc(&c->heavy_rounds, heavy_rounds);
   stc(&c->phase, phase);
 }
 
