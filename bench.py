@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
 
 WORKLOADS = {
     "rmat20": "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), symmetrised, deduplicated, int32 CSR",
@@ -58,6 +59,76 @@ def host_work_model(n, row_ptr, col):
     return {"support_pairs": pairs, "oriented_edges": int(before.sum()), "max_outdeg": int(dplus.max(initial=0))}
 
 
+def source_digest():
+    """Digest of the kernel sources; recorded traffic is valid only for the same sources."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1205_6693_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel, launches):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration), or
+    None if there is none for these sources."""
+    path = os.path.join(PROFILES, "traffic_%s_%s.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            a, b = line.split(":", 1)
+            kv[a.strip()] = b.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return int(float(kv["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(nbytes):
+    """A plain device copy of known size, for scaling the PMC byte counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.add(a, 0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4,
+                      "dispatches": 5}))
+
+
+def summarize(prof_dir):
+    """Text summary of rocprofv3 CSV output (kernel stats and counters)."""
+    import csv
+    import glob
+    out = []
+    for f in sorted(glob.glob(os.path.join(prof_dir, "**", "*kernel_stats.csv"), recursive=True)):
+        out.append("kernel stats: " + os.path.relpath(f, prof_dir))
+        for r in csv.DictReader(open(f)):
+            name = r.get("Name", r.get("KERNEL_NAME", "?")).replace("(anonymous namespace)::", "").replace("void ", "")
+            out.append("  %-60s calls=%s total_ns=%s avg_ns=%s" % (name[:60], r.get("Calls"), r.get("TotalDurationNs"),
+                                                                  r.get("AverageNs")))
+    for f in sorted(glob.glob(os.path.join(prof_dir, "**", "*counter_collection.csv"), recursive=True)):
+        agg = {}
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+            key = (name, r["Counter_Name"])
+            a = agg.setdefault(key, [0.0, set()])
+            a[0] += float(r["Counter_Value"])
+            a[1].add(r["Dispatch_Id"])
+        out.append("counters: " + os.path.relpath(f, prof_dir))
+        for (name, cname), (val, disp) in sorted(agg.items()):
+            out.append("  %-50s %-12s dispatches=%d total=%.6g per_dispatch=%.6g" % (name[-50:], cname, len(disp), val,
+                                                                                  val / max(1, len(disp))))
+    print("\n".join(out))
+
+
 def cpu_baseline(sample_scale: int, seed: int):
     import graphgen
     import oracle
@@ -85,7 +156,15 @@ def main():
     ap.add_argument("--support", default="auto", choices=["auto", "hash", "bsearch", "merge"])
     ap.add_argument("--cpu-sample-scale", type=int, default=17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, help="run a plain copy of this many bytes and exit")
+    ap.add_argument("--summarize", default="", help="summarise a rocprofv3 output directory and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -141,18 +220,24 @@ def main():
         return float(np.mean([x[key] for x in stats]))
 
     ms_sup, ms_peel, ms_build = avg("ms_support"), avg("ms_peel"), avg("ms_build")
+    ms_peel_kernel = avg("ms_peel_kernel")
     st = stats[-1]
+    launches = max(1, st["launches"])
     # algorithmic bytes (per-unit figures are documented in the design doc)
     sup_bytes = 4 * model["support_pairs"] + 24 * model["oriented_edges"] + 8 * st["triangles"]
     peel_bytes = 16 * st["peel_work"] + 44 * m
     kernels = {
-        "support": {"bytes": sup_bytes, "ms": ms_sup},
-        "peel": {"bytes": peel_bytes, "ms": ms_peel},
+        "support": {"bytes": sup_bytes, "ms": ms_sup, "launches": 1, "name": "support kernels"},
+        "peel": {"bytes": peel_bytes, "ms": ms_peel_kernel, "launches": launches, "name": "k_peel"},
     }
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    achieved = kernels[dom]["bytes"] / (kernels[dom]["ms"] * 1e-3) / 1e9
+    kd = kernels[dom]
+    achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, kd["name"], kd["launches"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom}
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kd["name"],
+                "launches_per_step": kd["launches"], "avg_launch_ms": round(kd["ms"] / kd["launches"], 4),
+                "bytes_per_launch": int(kd["bytes"] / kd["launches"])}
     result = {
         "metric": "truss-decomposed edges/s", "value": m / (ms_per_step * 1e-3), "unit": "edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -169,6 +254,7 @@ def main():
         "roofline": roofline,
         "roofline_all": {k: {"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2), "ms": round(v["ms"], 3),
                              "bytes": v["bytes"]} for k, v in kernels.items()},
+        "peel_kernel_ms": ms_peel_kernel,
     }
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)

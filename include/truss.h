@@ -129,6 +129,7 @@ typedef struct truss_stats {
   int64_t heavy_rounds;     /* sub-rounds in which long walks were cut into pieces */
   double ms_phase[6];       /* peeling time by phase: live-list sweep, level start,
                                frontier rounds, unused, dense re-scan, unused     */
+  double ms_peel_kernel;    /* time inside the persistent peeling kernel, all launches */
 } truss_stats;
 
 /* Fills *opts with defaults: AUTO strategies, heuristic scheduler. */

@@ -214,6 +214,7 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
     stats->heavy_rounds = pr.heavy_rounds;
     for (int b = 0; b < 6; ++b) stats->frontier_hist[b] = pr.hist[b];
     for (int b = 0; b < 6; ++b) stats->ms_phase[b] = pr.phase_ms[b];
+    stats->ms_peel_kernel = pr.kernel_ms;
   }
   return TRUSS_OK;
 }
@@ -340,6 +341,7 @@ int truss_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_
       stats->heavy_rounds += st.heavy_rounds;
       for (int b = 0; b < 6; ++b) stats->frontier_hist[b] += st.frontier_hist[b];
       for (int b = 0; b < 6; ++b) stats->ms_phase[b] += st.ms_phase[b];
+      stats->ms_peel_kernel += st.ms_peel_kernel;
     }
   }
   return TRUSS_OK;

@@ -85,6 +85,7 @@ struct PeelResult {
   int64_t heavy_rounds = 0;
   int64_t hist[6] = {0, 0, 0, 0, 0, 0};
   double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+  double kernel_ms = 0;  // time inside the persistent peeling kernel (all launches)
 };
 size_t peel_workspace(const DevGraph& dg, Arena& a);
 int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss_canon, Arena& a,

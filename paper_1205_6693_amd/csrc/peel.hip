@@ -849,14 +849,26 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
   void* args[] = {&P};
   PeelCtl h;
   int launches = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  const bool timed = hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
+  double kernel_ms = 0.0;
   for (;;) {
+    if (timed) (void)hipEventRecord(ev0, s);
     TRUSS_HIP(hipLaunchCooperativeKernel((const void*)k_peel, dim3(blocks), dim3(kT), args, 0, s));
+    if (timed) (void)hipEventRecord(ev1, s);
     ++launches;
     TRUSS_HIP(hipMemcpyAsync(&h, L.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));
     TRUSS_HIP(hipStreamSynchronize(s));
+    if (timed) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev0, ev1) == hipSuccess) kernel_ms += t;
+    }
     if (h.abort || h.err || h.phase != PH_COMPACT) break;
     hipLaunchKernelGGL(k_compact, dim3(2048), dim3(256), 0, s, dg.row_ptr, dg.col, dg.seid, L.rlen, dg.n, sr, L.ctl);
   }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  res->kernel_ms = kernel_ms;
   res->kmax = h.kmax;
   res->levels = h.levels;
   res->subrounds = h.subrounds;
