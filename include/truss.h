@@ -93,17 +93,23 @@ typedef struct truss_graph {
 #define TRUSS_PROBE_HASH 1    /* hash table over the edges, as Section 3.2 keeps E_G */
 #define TRUSS_PROBE_BSEARCH 2 /* binary search of the other endpoint's sorted row  */
 
-/* Scheduler used for TRUSS_SUP_AUTO / TRUSS_PEEL_AUTO decisions. */
-#define TRUSS_SCHED_PLAIN 0     /* fixed: bsearch support, dense sweep peeling  */
-#define TRUSS_SCHED_HEURISTIC 1 /* fixed thresholds                             */
-#define TRUSS_SCHED_LEARNED 2   /* MLP over per-level features (model below)    */
+/* Scheduler used for the AUTO decisions: the intersection strategy of each
+ * support bin (vertices grouped by out-degree) and, for each peeling level, the
+ * frontier mode and the membership probe.  Every choice computes the same
+ * supports and truss numbers; only the speed differs. */
+#define TRUSS_SCHED_PLAIN 0     /* fixed: merge support, dense sweep, bsearch probes */
+#define TRUSS_SCHED_HEURISTIC 1 /* fixed thresholds                                  */
+#define TRUSS_SCHED_LEARNED 2   /* MLP scores (see "Learned scheduler" below); the
+                                   heuristic is used when the model is absent or
+                                   malformed (truss_stats.sched_fallback = 1)       */
 
 typedef struct truss_options {
   int32_t version;          /* must be TRUSS_VERSION                           */
   int32_t support_strategy; /* TRUSS_SUP_*                                      */
   int32_t peel_mode;        /* TRUSS_PEEL_*                                     */
   int32_t scheduler;        /* TRUSS_SCHED_*                                    */
-  const float *model;       /* (device) learned-scheduler weights, or NULL     */
+  const float *model;       /* (device) learned-scheduler model (both parts, see
+                               truss_sched_model_floats), or NULL             */
   int64_t max_subrounds;    /* > 0: fail with TRUSS_E_INTERNAL past this many  */
   int32_t grid_blocks;      /* > 0: persistent-kernel workgroups (tuning)      */
   int32_t peel_probe;       /* TRUSS_PROBE_*                                    */
@@ -168,6 +174,87 @@ int truss_batch(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_
                 const int32_t *src, const int32_t *dst, int32_t *truss_out,
                 const truss_options *opts, truss_stats *stats, void *ws, size_t ws_bytes,
                 void *stream);
+
+/* ---- tracing: the per-decision record behind the learned scheduler ----- */
+/* Peeling level actions: bit 0 = probe (0 hash table, 1 binary search),
+ * bit 1 = frontier mode (0 sparse worklist, 1 dense re-scan). */
+#define TRUSS_SCHED_PEEL_F 8 /* features of a level, taken when its first frontier is known:
+                                log2(1+live edges), log2(1+|F_0|), |F_0|/live edges,
+                                log2(k), log2(1+W_0), log2(1+W_0/|F_0|) where W_0 is the
+                                summed shorter live row length over F_0,
+                                live edges / row entries kept, log2(1+sub-rounds of the
+                                previous level) */
+#define TRUSS_SCHED_PEEL_A 4
+/* Support bin actions: 0 LDS hash, 1 binary search, 2 merge (hash is not
+ * available to the last bin, whose out-neighbourhoods exceed the LDS). */
+#define TRUSS_SCHED_SUP_BINS 4 /* out-degree 2..64, 65..1024, 1025..4096, larger */
+#define TRUSS_SCHED_SUP_F 6  /* log2(1+vertices), log2(1+sum d), log2(1+sum d^2),
+                                log2(1+mean d), log2(1+m), log2(1+sum d^2 / sum d) */
+#define TRUSS_SCHED_SUP_A 3
+
+typedef struct truss_trace {
+  int32_t level_cap;      /* (in) rows available in the level arrays (may be 0)        */
+  int32_t levels;         /* (out) levels recorded: min(levels peeled, level_cap)      */
+  float *level_feat;      /* (device) level_cap x TRUSS_SCHED_PEEL_F raw features      */
+  float *level_ms;        /* (device) level_cap: time from the level's decision to its
+                             last sub-round's end (same state at that point under
+                             every action, so times of different runs compare)        */
+  int32_t *level_action;  /* (device) level_cap: action taken                          */
+  int32_t sup_action[TRUSS_SCHED_SUP_BINS];              /* (out) action per bin       */
+  float sup_feat[TRUSS_SCHED_SUP_BINS][TRUSS_SCHED_SUP_F]; /* (out) raw features      */
+  float sup_ms[TRUSS_SCHED_SUP_BINS];                    /* (out) time of each bin     */
+} truss_trace;
+
+/* truss_decompose that also records every scheduling decision, its features
+ * and its time (trace: host struct; its arrays are device memory).  The
+ * extra timing events make it slightly slower than truss_decompose. */
+int truss_decompose_traced(const truss_graph *g, int32_t *truss_out, const truss_options *opts,
+                           truss_stats *stats, truss_trace *trace, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* ---- learned scheduler: the network and its training ----------------- */
+/* Two-layer perceptron y = W2 tanh(W1 x + b1) + b2 in fp32.  params packs
+ * W1[H][F], b1[H], W2[O][H], b2[O], row-major; X is B x F and Y is B x O,
+ * row-major.  Limits: 1 <= F <= 16, 1 <= H <= 64, 1 <= O <= 8, B >= 1. */
+#define TRUSS_MLP_MAX_F 16
+#define TRUSS_MLP_MAX_H 64
+#define TRUSS_MLP_MAX_O 8
+
+/* Number of floats in params, or TRUSS_E_INVAL. */
+int truss_mlp_param_count(int32_t F, int32_t H, int32_t O);
+int truss_mlp_workspace_size(int32_t F, int32_t H, int32_t O, int32_t B, size_t *bytes);
+/* Y = network(X). */
+int truss_mlp_forward(const float *params, int32_t F, int32_t H, int32_t O, const float *X,
+                      int32_t B, float *Y, void *ws, size_t ws_bytes, void *stream);
+/* grad = d(sum_{r,o} dY[r,o] * Y[r,o]) / d params (the vector-Jacobian product). */
+int truss_mlp_backward(const float *params, int32_t F, int32_t H, int32_t O, const float *X,
+                       int32_t B, const float *dY, float *grad, void *ws, size_t ws_bytes,
+                       void *stream);
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, step size
+ * lr) on the loss L = sum_{r,o} Wt[r,o] (Y[r,o] - T[r,o])^2 / sum Wt, where Y
+ * = network(X).  params, adam_m, adam_v (device, param_count floats each) are
+ * updated in place; step0 is the number of Adam steps already taken (bias
+ * correction).  loss (host, nullable) receives L after the last step.  The sum
+ * of Wt must be positive. */
+int truss_mlp_train(float *params, float *adam_m, float *adam_v, int32_t F, int32_t H, int32_t O,
+                    const float *X, const float *T, const float *Wt, int32_t B, int32_t steps,
+                    int32_t step0, float lr, float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* The model passed in truss_options.model is two parts back to back, peeling
+ * first, then support.  A part is [1205, F, H, O, mu[F], isd[F], params] in
+ * floats; the network sees (x - mu) * isd and each output estimates log2 of
+ * the action's time in ms.  kind: 0 = peeling, 1 = support. */
+int truss_sched_part_floats(int32_t kind, int32_t H);
+int truss_sched_model_floats(int32_t H);
+int truss_sched_train_workspace_size(int32_t kind, int32_t H, int32_t B, size_t *bytes);
+/* Fits one model part on B traced decisions: X (device) B x F raw features,
+ * T_ms (device) B x A times of every action (<= 0 where not measured).  Sets
+ * the normalisation from X, initialises the weights from `seed`, and trains
+ * with a weighted log2-time loss in which a row's weight grows with its
+ * slowest measured time.  part (device) receives truss_sched_part_floats. */
+int truss_sched_train(int32_t kind, const float *X, const float *T_ms, int32_t B, int32_t H,
+                      int32_t steps, float lr, uint64_t seed, float *part, float *loss,
+                      void *ws, size_t ws_bytes, void *stream);
 
 const char *truss_strerror(int code);
 const char *truss_last_error(void);

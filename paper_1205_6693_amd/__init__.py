@@ -8,6 +8,8 @@ Entry points mirror the C ABI in include/truss.h:
     truss_decompose(graph, ...)       -> (truss int32[m] cuda tensor, stats dict)
     truss_batch(vtx_off, edge_off, src, dst, ...) -> (truss int32[M], stats dict)
     truss_workspace_size(graph)       -> bytes
+    truss_decompose_traced(graph, ...) -> (truss, stats, trace dict)
+    mlp_forward / mlp_backward / mlp_train / sched_train -> the scheduler network
 Graphs are built with Graph.from_edges(n, src, dst) or
 Graph.from_csr(n, row_ptr, col) from int32/int64 CUDA tensors.
 """
@@ -28,6 +30,7 @@ SUP_AUTO, SUP_HASH, SUP_BSEARCH, SUP_MERGE = 0, 1, 2, 3
 PEEL_AUTO, PEEL_SPARSE, PEEL_DENSE = 0, 1, 2
 PROBE_AUTO, PROBE_HASH, PROBE_BSEARCH = 0, 1, 2
 SCHED_PLAIN, SCHED_HEURISTIC, SCHED_LEARNED = 0, 1, 2
+SCHED_PEEL_F, SCHED_PEEL_A, SCHED_SUP_BINS, SCHED_SUP_F, SCHED_SUP_A = 8, 4, 4, 6, 3
 
 
 class TrussError(RuntimeError):
@@ -67,6 +70,15 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Trace(ctypes.Structure):
+    _fields_ = [("level_cap", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("level_feat", ctypes.c_void_p), ("level_ms", ctypes.c_void_p),
+                ("level_action", ctypes.c_void_p),
+                ("sup_action", ctypes.c_int32 * SCHED_SUP_BINS),
+                ("sup_feat", (ctypes.c_float * SCHED_SUP_F) * SCHED_SUP_BINS),
+                ("sup_ms", ctypes.c_float * SCHED_SUP_BINS)]
+
+
 _lib = None
 
 
@@ -93,8 +105,25 @@ def load_library():
     lib.truss_decompose.argtypes = [gp, vp, op, sp, vp, ctypes.c_size_t, vp]
     lib.truss_batch_workspace_size.argtypes = [i32, vp, vp, op, ctypes.POINTER(ctypes.c_size_t)]
     lib.truss_batch.argtypes = [i32, vp, vp, vp, vp, vp, op, sp, vp, ctypes.c_size_t, vp]
+    tp = ctypes.POINTER(Trace)
+    f32, u64, fp = ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    lib.truss_decompose_traced.argtypes = [gp, vp, op, sp, tp, vp, ctypes.c_size_t, vp]
+    lib.truss_mlp_param_count.argtypes = [i32, i32, i32]
+    lib.truss_mlp_workspace_size.argtypes = [i32, i32, i32, i32, szp]
+    lib.truss_mlp_forward.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, ctypes.c_size_t, vp]
+    lib.truss_mlp_backward.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.truss_mlp_train.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, i32, i32, i32, f32, fp, vp,
+                                    ctypes.c_size_t, vp]
+    lib.truss_sched_part_floats.argtypes = [i32, i32]
+    lib.truss_sched_model_floats.argtypes = [i32]
+    lib.truss_sched_train_workspace_size.argtypes = [i32, i32, i32, szp]
+    lib.truss_sched_train.argtypes = [i32, vp, vp, i32, i32, i32, f32, u64, vp, fp, vp, ctypes.c_size_t, vp]
     for f in ("truss_workspace_size", "truss_support", "truss_decompose",
-              "truss_batch_workspace_size", "truss_batch", "truss_version"):
+              "truss_batch_workspace_size", "truss_batch", "truss_version", "truss_decompose_traced",
+              "truss_mlp_param_count", "truss_mlp_workspace_size", "truss_mlp_forward",
+              "truss_mlp_backward", "truss_mlp_train", "truss_sched_part_floats",
+              "truss_sched_model_floats", "truss_sched_train_workspace_size", "truss_sched_train"):
         getattr(lib, f).restype = ctypes.c_int
     lib.truss_strerror.argtypes = [ctypes.c_int]
     lib.truss_strerror.restype = ctypes.c_char_p
@@ -249,3 +278,124 @@ def truss_batch(vtx_off, edge_off, src, dst, opts: Options | None = None, out=No
                            ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
                            _stream(stream)))
     return out, st.to_dict()
+
+
+def truss_decompose_traced(graph: Graph, opts: Options | None = None, level_cap: int = 4096, out=None,
+                           ws=None, stream=None):
+    """truss_decompose plus the scheduler's record: per level the raw features,
+    the time from the decision to the level's end and the action taken; per
+    support bin the features, time and action."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    if ws is None:
+        ws = workspace(graph, opts)
+    feat = torch.zeros((max(level_cap, 1), SCHED_PEEL_F), dtype=torch.float32, device=graph.device)
+    lms = torch.zeros(max(level_cap, 1), dtype=torch.float32, device=graph.device)
+    lact = torch.full((max(level_cap, 1),), -1, dtype=torch.int32, device=graph.device)
+    tr = Trace()
+    tr.level_cap = level_cap
+    tr.level_feat, tr.level_ms, tr.level_action = _ptr(feat).value, _ptr(lms).value, _ptr(lact).value
+    st = Stats()
+    g = graph._c()
+    _check(lib.truss_decompose_traced(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
+                                      ctypes.byref(st), ctypes.byref(tr), _ptr(ws), ws.numel(),
+                                      _stream(stream)))
+    L = tr.levels
+    trace = {"levels": L,
+             "level_feat": feat[:L].cpu().numpy(),
+             "level_ms": lms[:L].cpu().numpy(),
+             "level_action": lact[:L].cpu().numpy(),
+             "sup_action": [int(x) for x in tr.sup_action],
+             "sup_feat": [[float(v) for v in row] for row in tr.sup_feat],
+             "sup_ms": [float(x) for x in tr.sup_ms]}
+    return out, st.to_dict(), trace
+
+
+def _f32(t):
+    torch = _torch()
+    return t.to(torch.float32).contiguous()
+
+
+def mlp_param_count(F: int, H: int, O: int) -> int:
+    rc = load_library().truss_mlp_param_count(F, H, O)
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def _mlp_ws(F, H, O, B, device):
+    torch = _torch()
+    b = ctypes.c_size_t(0)
+    _check(load_library().truss_mlp_workspace_size(F, H, O, B, ctypes.byref(b)))
+    return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+
+def mlp_forward(params, X, H: int, O: int, stream=None):
+    """Network outputs (B x O) for inputs X (B x F), all CUDA float32."""
+    torch = _torch()
+    X = _f32(X)
+    params = _f32(params)
+    B, F = X.shape
+    Y = torch.empty((B, O), dtype=torch.float32, device=X.device)
+    ws = _mlp_ws(F, H, O, B, X.device)
+    _check(load_library().truss_mlp_forward(_ptr(params), F, H, O, _ptr(X), B, _ptr(Y), _ptr(ws), ws.numel(),
+                                            _stream(stream)))
+    return Y
+
+
+def mlp_backward(params, X, dY, H: int, stream=None):
+    """d(sum dY * network(X)) / d params."""
+    torch = _torch()
+    X, dY, params = _f32(X), _f32(dY), _f32(params)
+    B, F = X.shape
+    O = dY.shape[1]
+    grad = torch.empty(params.numel(), dtype=torch.float32, device=X.device)
+    ws = _mlp_ws(F, H, O, B, X.device)
+    _check(load_library().truss_mlp_backward(_ptr(params), F, H, O, _ptr(X), B, _ptr(dY), _ptr(grad), _ptr(ws),
+                                             ws.numel(), _stream(stream)))
+    return grad
+
+
+def mlp_train(params, adam_m, adam_v, X, T, Wt, H: int, steps: int, step0: int = 0, lr: float = 1e-2,
+              stream=None):
+    """Adam steps on the weighted squared error, in place on params/adam_m/adam_v
+    (contiguous CUDA float32 tensors); returns the final loss."""
+    X, T, Wt = _f32(X), _f32(T), _f32(Wt)
+    B, F = X.shape
+    O = T.shape[1]
+    ws = _mlp_ws(F, H, O, B, X.device)
+    loss = ctypes.c_float(0.0)
+    _check(load_library().truss_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), F, H, O, _ptr(X), _ptr(T),
+                                          _ptr(Wt), B, steps, step0, lr, ctypes.byref(loss), _ptr(ws),
+                                          ws.numel(), _stream(stream)))
+    return loss.value
+
+
+def sched_part_floats(kind: int, H: int) -> int:
+    rc = load_library().truss_sched_part_floats(kind, H)
+    if rc < 0:
+        _check(rc)
+    return rc
+
+
+def sched_train(kind: int, X, T_ms, H: int = 32, steps: int = 3000, lr: float = 1e-2, seed: int = 1,
+                out=None, stream=None):
+    """Fit a scheduler model part (kind 0 peeling, 1 support) on traced
+    decisions: X (B x F) raw features, T_ms (B x A) action times (<= 0 = not
+    measured).  Returns (part float32 tensor, final loss)."""
+    torch = _torch()
+    lib = load_library()
+    X, T_ms = _f32(X), _f32(T_ms)
+    B = X.shape[0]
+    n = sched_part_floats(kind, H)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=X.device)
+    b = ctypes.c_size_t(0)
+    _check(lib.truss_sched_train_workspace_size(kind, H, B, ctypes.byref(b)))
+    ws = torch.empty(b.value, dtype=torch.uint8, device=X.device)
+    loss = ctypes.c_float(0.0)
+    _check(lib.truss_sched_train(kind, _ptr(X), _ptr(T_ms), B, H, steps, lr, seed, _ptr(out),
+                                 ctypes.byref(loss), _ptr(ws), ws.numel(), _stream(stream)))
+    return out, loss.value

@@ -5,6 +5,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "mlp.hpp"
 
 namespace truss {
 
@@ -75,20 +76,58 @@ int check_opts(const truss_options* o) {
   return TRUSS_OK;
 }
 
-// Resolve AUTO choices of the scheduler into concrete strategies.
-void resolve(const truss_options* in, truss_options* out, int* fallback) {
-  truss_default_options(out);
-  if (in) *out = *in;
+// Checks a learned model's two part headers (device memory) against the
+// network shapes the scheduler evaluates; fills the part pointers.
+bool model_parts(const float* model, const float** peel_part, const float** sup_part, hipStream_t s) {
+  if (!model) return false;
+  float h[4];
+  if (hipMemcpyAsync(h, model, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  if (h[0] != kModelTag || h[1] != (float)kPeelF || h[3] != (float)kPeelA || !(h[2] >= 1.f) ||
+      !(h[2] <= (float)kMlpMaxH) || h[2] != (float)(int)h[2])
+    return false;
+  const int off = model_part_floats(kPeelF, (int)h[2], kPeelA);
+  float g[4];
+  if (hipMemcpyAsync(g, model + off, sizeof(g), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+  if (hipStreamSynchronize(s) != hipSuccess) return false;
+  if (g[0] != kModelTag || g[1] != (float)kSupF || g[3] != (float)kSupA || !(g[2] >= 1.f) ||
+      !(g[2] <= (float)kMlpMaxH) || g[2] != (float)(int)g[2])
+    return false;
+  *peel_part = model;
+  *sup_part = model + off;
+  return true;
+}
+
+// Resolves the options into the support and peeling plans.  A learned
+// scheduler without a well-formed model falls back to the heuristic.
+void resolve(const truss_options* in, SupPlan* sp, PeelPlan* pp, int* fallback, hipStream_t s) {
+  truss_options o;
+  truss_default_options(&o);
+  if (in) o = *in;
   *fallback = 0;
-  int sched = out->scheduler;
-  if (sched == TRUSS_SCHED_LEARNED && out->model == nullptr) {
+  int sched = o.scheduler;
+  const float *peel_part = nullptr, *sup_part = nullptr;
+  if (sched == TRUSS_SCHED_LEARNED && !model_parts(o.model, &peel_part, &sup_part, s)) {
     *fallback = 1;
     sched = TRUSS_SCHED_HEURISTIC;
   }
-  if (out->support_strategy == TRUSS_SUP_AUTO)
-    out->support_strategy = sched == TRUSS_SCHED_PLAIN ? TRUSS_SUP_BSEARCH : TRUSS_SUP_HASH;
-  if (out->peel_mode == TRUSS_PEEL_AUTO && sched == TRUSS_SCHED_PLAIN) out->peel_mode = TRUSS_PEEL_DENSE;
-  if (out->peel_mode == TRUSS_PEEL_AUTO) out->peel_mode = TRUSS_PEEL_SPARSE;
+  *sp = SupPlan();
+  sp->sched = sched;
+  sp->force = o.support_strategy == TRUSS_SUP_AUTO ? -1 : o.support_strategy - 1;
+  sp->model = sup_part;
+  *pp = PeelPlan();
+  pp->sched = sched;
+  pp->model = peel_part;
+  if (o.peel_probe != TRUSS_PROBE_AUTO) {
+    pp->fix_bits |= 1;
+    pp->fix_vals |= o.peel_probe == TRUSS_PROBE_BSEARCH ? 1 : 0;
+  }
+  if (o.peel_mode != TRUSS_PEEL_AUTO) {
+    pp->fix_bits |= 2;
+    pp->fix_vals |= o.peel_mode == TRUSS_PEEL_DENSE ? 2 : 0;
+  }
+  pp->max_subrounds = o.max_subrounds;
+  pp->grid_blocks = o.grid_blocks;
 }
 
 struct Plan {
@@ -140,15 +179,22 @@ struct Timer {
 
 // Runs build + support, then either scatters sup (want_truss false) or peels.
 int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* triangles,
-               const truss_options* opts_in, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s) {
+               const truss_options* opts_in, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s,
+               truss_trace* trace) {
   int rc = check_graph(g);
   if (rc) return rc;
   rc = check_opts(opts_in);
   if (rc) return rc;
   if (g->m > 0 && !out) { set_last_error("output is NULL"); return TRUSS_E_INVAL; }
-  truss_options opts;
-  int fallback = 0;
-  resolve(opts_in, &opts, &fallback);
+  if (trace && trace->level_cap < 0) { set_last_error("negative trace capacity"); return TRUSS_E_INVAL; }
+  if (trace) {
+    trace->levels = 0;
+    for (int b = 0; b < kSupBins; ++b) {
+      trace->sup_action[b] = -1;
+      trace->sup_ms[b] = 0.f;
+      for (int i = 0; i < kSupF; ++i) trace->sup_feat[b][i] = 0.f;
+    }
+  }
   Arena need;
   need.counting = true;
   Plan dummy;
@@ -163,6 +209,10 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
   Plan p;
   p.d_err = a.take<int>(64);
   p.d_total = a.take<unsigned long long>(8);
+  SupPlan sp;
+  PeelPlan pp;
+  int fallback = 0;
+  resolve(opts_in, &sp, &pp, &fallback, s);
   Timer tm(stats != nullptr, s);
   tm.mark(0);
   DevGraph dg;
@@ -171,7 +221,7 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
   tm.mark(1);
   p.sr = a.take<int2>((size_t)g->m + 1);
   p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
-  rc = compute_support(dg, opts.support_strategy, p.sr, a, s);
+  rc = compute_support(dg, sp, p.sr, a, s, trace);
   if (rc) return rc;
   tm.mark(2);
   PeelResult pr;
@@ -187,7 +237,7 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
   } else {
     if (stats && g->m > 0) hipLaunchKernelGGL(k_sum_sup, dim3(1024), dim3(kT), 0, s, p.sr, g->m, p.d_total);
     int32_t* tc = g->fmt == TRUSS_FMT_EDGES ? p.truss_canon : out;
-    rc = peel(dg, &opts, p.sr, tc, a, &pr, s);
+    rc = peel(dg, pp, p.sr, tc, a, &pr, s, trace);
     if (rc) return rc;
     if (g->fmt == TRUSS_FMT_EDGES && g->m > 0)
       hipLaunchKernelGGL(k_scatter_out, dim3(grid_for(g->m)), dim3(kT), 0, s, tc, dg.perm, g->m, out);
@@ -270,13 +320,20 @@ int truss_support(const truss_graph* g, int32_t* sup_out, int64_t* triangles, vo
                   void* stream) {
   if (triangles) *triangles = 0;
   if (g && g->m > 0 && !sup_out) { set_last_error("sup_out is NULL"); return TRUSS_E_INVAL; }
-  return run_single(g, false, sup_out, triangles, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream);
+  return run_single(g, false, sup_out, triangles, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int truss_decompose(const truss_graph* g, int32_t* truss_out, const truss_options* opts, truss_stats* stats,
                     void* ws, size_t ws_bytes, void* stream) {
   if (g && g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
-  return run_single(g, true, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream);
+  return run_single(g, true, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+int truss_decompose_traced(const truss_graph* g, int32_t* truss_out, const truss_options* opts, truss_stats* stats,
+                           truss_trace* trace, void* ws, size_t ws_bytes, void* stream) {
+  if (!trace) { set_last_error("trace is NULL"); return TRUSS_E_INVAL; }
+  if (g && g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
+  return run_single(g, true, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, trace);
 }
 
 int truss_batch_workspace_size(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,

@@ -73,9 +73,26 @@ struct BuildBufs;
 size_t build_workspace(const truss_graph* g, Arena& a);
 int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStream_t s);
 
+// Scheduling of the exact methods (the scheduler never changes results).
+struct SupPlan {
+  int sched = TRUSS_SCHED_HEURISTIC;  // effective scheduler for the bins
+  int force = -1;                     // >= 0: this method (0 hash, 1 bsearch, 2 merge) in every bin
+  const float* model = nullptr;       // (device) support model part when learned
+};
+struct PeelPlan {
+  int sched = TRUSS_SCHED_HEURISTIC;  // effective scheduler for the levels
+  int fix_bits = 0;                   // action bits fixed by the options (bit 0 probe, bit 1 mode)
+  int fix_vals = 0;                   // their values
+  const float* model = nullptr;       // (device) peeling model part when learned
+  long long max_subrounds = 0;
+  int grid_blocks = 0;
+};
+
 // Support: sr[e].x = sup(e) for every canonical edge (sr must be zeroed inside).
+// trace (nullable): receives each bin's method, features and time.
 size_t support_workspace(const DevGraph& dg, Arena& a);
-int compute_support(const DevGraph& dg, int strategy, int2* sr, Arena& a, hipStream_t s);
+int compute_support(const DevGraph& dg, const SupPlan& plan, int2* sr, Arena& a, hipStream_t s,
+                    truss_trace* trace);
 
 // Peeling: truss[e] for every canonical edge; sr holds sup on entry.
 struct PeelResult {
@@ -88,8 +105,8 @@ struct PeelResult {
   double kernel_ms = 0;  // time inside the persistent peeling kernel (all launches)
 };
 size_t peel_workspace(const DevGraph& dg, Arena& a);
-int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss_canon, Arena& a,
-         PeelResult* res, hipStream_t s);
+int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_canon, Arena& a,
+         PeelResult* res, hipStream_t s, truss_trace* trace);
 
 void set_last_error(const char* fmt, ...);
 int device_grid_blocks(const void* kernel, int block, size_t lds);

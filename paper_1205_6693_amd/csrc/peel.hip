@@ -34,11 +34,16 @@
 // operations before its workgroup arrives.  Adjacency rows, offsets and row
 // lengths are immutable inside a launch and use ordinary cached loads.
 //
-// Frontier modes per level: SPARSE enqueues an edge the moment its support
-// drops from k-1 to k-2 (the queue of Section 3.1); DENSE re-scans the live
-// edges after every sub-round.
+// Each level runs in one of four ways, decided when its first frontier is
+// known: the frontier mode (SPARSE enqueues an edge the moment its support
+// drops from k-1 to k-2, the queue of Section 3.1; DENSE re-scans the live
+// edges after every sub-round) and the membership probe of Step 8 (the edge
+// hash table, or binary search of the other endpoint's row).  The scheduler
+// (plain, a fixed heuristic, or the learned network evaluated by the control
+// wavefront) only picks among these exact methods.
 #include "common.hpp"
 #include "internal.hpp"
+#include "mlp.hpp"
 
 namespace truss {
 
@@ -78,6 +83,7 @@ struct alignas(256) PeelCtl {
   alignas(128) int w_chunks;              // frontier chunks finished
   alignas(128) unsigned long long w_pieces;  // segments announced (may exceed the slot capacity)
   alignas(128) unsigned long long w_work;
+  alignas(128) unsigned long long w_fwork;  // level start: sum over F_0 of the shorter live row
   alignas(128) int pad3;
   // published control state, written only by the control step
   int phase;
@@ -101,8 +107,15 @@ struct alignas(256) PeelCtl {
   unsigned long long t_phase[8];        // time spent per phase (100 MHz ticks)
   int err;
   int abort;
-  int force_mode;
   int launches;
+  // scheduling
+  int probe;               // membership probe of the current level: 0 hash table, 1 binary search
+  int sched;               // TRUSS_SCHED_* in effect
+  int fix_bits, fix_vals;  // action bits fixed by the options
+  int m_edges;
+  long long lvl_sub0;      // sub-rounds before the current level
+  long long prev_sub;      // sub-rounds of the previous level
+  unsigned long long t_dec;  // wall clock at the current level's decision
 };
 
 struct PeelArgs {
@@ -126,8 +139,12 @@ struct PeelArgs {
   int32_t* rec_tot;           // per chunk of 64 positions: total walk length
   const EdgeSlot* etab;       // edge hash table
   unsigned long long etab_mask;
-  int probe;                  // 0: hash table lookup, 1: binary search of the row
   PeelCtl* ctl;
+  const float* model;         // peeling model part (learned scheduler), or null
+  float* tr_feat;             // per-level trace (tr_cap rows), or null
+  float* tr_ms;
+  int32_t* tr_act;
+  int tr_cap;
 };
 
 // ---- coherent (agent-scope relaxed) accesses ---------------------------------------
@@ -154,17 +171,25 @@ __device__ __forceinline__ int hist_bin(long long q) {
   return q <= 1 ? 0 : q <= 16 ? 1 : q <= 256 ? 2 : q <= 4096 ? 3 : q <= 65536 ? 4 : 5;
 }
 
-// ---- control step: one thread of the last workgroup to reach a barrier -----------------------
+// The heuristic's action for a level (bit 0 probe, bit 1 mode).
+__device__ __forceinline__ int heuristic_action(const float* x) {
+  (void)x;
+  return 0;
+}
+
+// ---- control step: the first wavefront of the last workgroup to reach a barrier ---------------
 // All inputs are loaded first (independent loads in flight together), the
-// decision is made in registers, and the outputs are stored at the end.
-__device__ void control_step(PeelCtl* c) {
+// decision is made in registers, and lane 0 stores the outputs at the end.
+// Every value is the same in all lanes; the lanes evaluate the scheduler's
+// network together (one hidden unit each).
+__device__ void control_step(PeelCtl* c, const PeelArgs& P) {
+  const bool lead = lane_id() == 0;
   int phase = ldc(&c->phase);
   int k = ldc(&c->k);
   int r = ldc(&c->r);
   int acnt = ldc(&c->acnt);
   int acur = ldc(&c->acur);
   const int mode_in = ldc(&c->mode);
-  const int force = ldc(&c->force_mode);
   int levels = ldc(&c->levels);
   long long removed_level = ldc(&c->removed_level);
   long long csr_live = ldc(&c->csr_live);
@@ -176,10 +201,18 @@ __device__ void control_step(PeelCtl* c) {
   const int w_alive = ldc(&c->w_alive);
   const int w_minsup = ldc(&c->w_minsup);
   const unsigned long long w_pieces = ldc(&c->w_pieces);
+  const unsigned long long w_fwork = ldc(&c->w_fwork);
+  const int sched = ldc(&c->sched);
+  const int fix_bits = ldc(&c->fix_bits);
+  const int fix_vals = ldc(&c->fix_vals);
+  long long lvl_sub0 = ldc(&c->lvl_sub0);
+  long long prev_sub = ldc(&c->prev_sub);
+  unsigned long long t_dec = ldc(&c->t_dec);
   const int phase_in = phase;
   const unsigned long long now = wall_clock64();
-  int qlen_out = -1, mode_out = -1, first_out = -1, hist_bin_out = -1;
+  int qlen_out = -1, mode_out = -1, probe_out = -1, first_out = -1, hist_bin_out = -1;
   bool reset_sweep = false, reset_queue = false, reset_proc = false;
+  const int li = levels - 1;  // trace row of the current level
 
   auto begin_round = [&](int q) {
     qlen_out = q;
@@ -194,7 +227,10 @@ __device__ void control_step(PeelCtl* c) {
       removed_level += w_qlen;
       begin_round(w_qlen);
     } else {
-      // level finished: compact the rows when the live count has halved
+      // level finished
+      if (lead && li < P.tr_cap && P.tr_ms) P.tr_ms[li] = (float)((double)(now - t_dec) * 1e-5);
+      prev_sub = subrounds - lvl_sub0;
+      // compact the rows when the live count has halved
       const long long alive_after = (long long)acnt - removed_level;
       if (alive_after > 0 && alive_after * 2 < csr_live) {
         csr_live = alive_after;
@@ -218,15 +254,49 @@ __device__ void control_step(PeelCtl* c) {
       levels += 1;
       r += 1;
       removed_level = 0;
-      mode_out = force == TRUSS_PEEL_DENSE ? (int)TRUSS_PEEL_DENSE : (int)TRUSS_PEEL_SPARSE;
       reset_queue = true;
       phase = PH_START;
       break;
     case PH_START:
       reset_queue = true;
       removed_level = w_qlen;
-      if (w_qlen > 0) begin_round(w_qlen);
-      else phase = PH_SWEEP;
+      if (w_qlen > 0) {
+        // the level's decision, from features that are the same whatever
+        // earlier levels chose
+        float x[kPeelF];
+        const float live = (float)acnt, f0 = (float)w_qlen, wk = (float)w_fwork;
+        x[0] = log2f(1.f + live);
+        x[1] = log2f(1.f + f0);
+        x[2] = f0 / (live > 1.f ? live : 1.f);
+        x[3] = log2f((float)k);
+        x[4] = log2f(1.f + wk);
+        x[5] = log2f(1.f + wk / (f0 > 1.f ? f0 : 1.f));
+        x[6] = live / (float)(csr_live > 1 ? csr_live : 1);
+        x[7] = log2f(1.f + (float)prev_sub);
+        int act;
+        if (sched == TRUSS_SCHED_LEARNED && P.model) {
+          float sc[kPeelA];
+          mlp_scores_wave(P.model, x, sc);
+          unsigned mask = 0;
+          for (int a = 0; a < kPeelA; ++a)
+            if ((a & fix_bits) == fix_vals) mask |= 1u << a;
+          act = argmin_allowed(sc, kPeelA, mask);
+        } else {
+          const int pref = sched == TRUSS_SCHED_PLAIN ? 3 : heuristic_action(x);
+          act = (pref & ~fix_bits) | fix_vals;
+        }
+        mode_out = (act & 2) ? (int)TRUSS_PEEL_DENSE : (int)TRUSS_PEEL_SPARSE;
+        probe_out = act & 1;
+        if (lead && li < P.tr_cap && P.tr_feat) {
+          for (int i = 0; i < kPeelF; ++i) P.tr_feat[(int64_t)li * kPeelF + i] = x[i];
+          P.tr_act[li] = act;
+        }
+        lvl_sub0 = subrounds;
+        t_dec = now;
+        begin_round(w_qlen);
+      } else {
+        phase = PH_SWEEP;
+      }
       break;
     case PH_PROC:
       reset_proc = true;
@@ -245,9 +315,10 @@ __device__ void control_step(PeelCtl* c) {
       phase = PH_DONE;
   }
   if (maxsr > 0 && subrounds > maxsr && phase != PH_DONE) {
-    stc(&c->err, (int)TRUSS_E_INTERNAL);
+    if (lead) stc(&c->err, (int)TRUSS_E_INTERNAL);
     phase = PH_DONE;
   }
+  if (!lead) return;
   // outputs
   if (t_last != 0 && phase_in >= 0 && phase_in < 8)
     stc(&c->t_phase[phase_in], ldc(&c->t_phase[phase_in]) + (now - t_last));
@@ -256,6 +327,7 @@ __device__ void control_step(PeelCtl* c) {
   if (reset_sweep) {
     stc(&c->w_alive, 0);
     stc(&c->w_minsup, kIntMax);
+    stc(&c->w_fwork, 0ULL);
   }
   if (reset_queue) {
     stc(&c->w_qlen, 0);
@@ -268,6 +340,7 @@ __device__ void control_step(PeelCtl* c) {
   }
   if (qlen_out >= 0) stc(&c->qlen, qlen_out);
   if (mode_out >= 0) stc(&c->mode, mode_out);
+  if (probe_out >= 0) stc(&c->probe, probe_out);
   if (first_out >= 0) stc(&c->first, first_out);
   stc(&c->k, k);
   stc(&c->kmax, k);
@@ -279,19 +352,22 @@ __device__ void control_step(PeelCtl* c) {
   stc(&c->csr_live, csr_live);
   stc(&c->subrounds, subrounds);
   stc(&c->heavy_rounds, heavy_rounds);
+  stc(&c->lvl_sub0, lvl_sub0);
+  stc(&c->prev_sub, prev_sub);
+  stc(&c->t_dec, t_dec);
   stc(&c->phase, phase);
 }
 
 // Grid barrier without cache maintenance (see the coherence note above); the
-// last workgroup to arrive runs control_step before release.  Returns false if
-// the wait timed out, and the kernel then winds down.
-__device__ bool phase_barrier(PeelCtl* c) {
-  __shared__ int s_ok;
+// first wavefront of the last workgroup to arrive runs control_step before
+// release.  Returns false if the wait timed out, and the kernel then winds down.
+__device__ bool phase_barrier(PeelCtl* c, const PeelArgs& P) {
+  __shared__ int s_ok, s_last;
   mem_wait();
   __syncthreads();
+  unsigned gen = 0;
   if (threadIdx.x == 0) {
-    int ok = 1;
-    const unsigned gen = ldc(&c->bar_gen);
+    gen = ldc(&c->bar_gen);
     // two-level arrival: the last workgroup of a group arrives for the group
     const unsigned g = blockIdx.x % kGroups;
     const unsigned gsize = (gridDim.x - g + kGroups - 1) / kGroups;
@@ -304,22 +380,28 @@ __device__ bool phase_barrier(PeelCtl* c) {
       const unsigned prev = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = prev == ngroups - 1;
     }
-    if (last) {
-      control_step(c);
+    s_last = last ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_last) {
+    if (threadIdx.x < kWave) control_step(c, P);
+    if (threadIdx.x == 0) {
       stc(&c->bar_count, 0u);
       mem_wait();
       __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const uint64_t t0 = wall_clock64();
-      while (ldc(&c->bar_gen) == gen) {
-        __builtin_amdgcn_s_sleep(1);
-        if (ldc(&c->abort)) { ok = 0; break; }
-        // 100 MHz constant clock: give up after 30 s
-        if (wall_clock64() - t0 > 3000000000ULL) {
-          stc(&c->abort, 1);
-          ok = 0;
-          break;
-        }
+      s_ok = 1;
+    }
+  } else if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint64_t t0 = wall_clock64();
+    while (ldc(&c->bar_gen) == gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if (ldc(&c->abort)) { ok = 0; break; }
+      // 100 MHz constant clock: give up after 30 s
+      if (wall_clock64() - t0 > 3000000000ULL) {
+        stc(&c->abort, 1);
+        ok = 0;
+        break;
       }
     }
     s_ok = ok;
@@ -333,7 +415,7 @@ __device__ __forceinline__ bool removed_at(int rnd, int r) { return rnd != 0 && 
 // One adjacency entry j of the walk of frontier edge e = (a, b).  Outputs the
 // (up to two) edges whose support crossed k-1 -> k-2 and must be enqueued.
 __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int32_t b, int64_t j, int r, int l, int k,
-                                              bool sparse, int32_t& f1, int32_t& f2) {
+                                              bool sparse, int probe, int32_t& f1, int32_t& f2) {
   f1 = -1;
   f2 = -1;
   const int32_t w = P.col[j];
@@ -342,7 +424,7 @@ __device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int3
   const int rnd1 = ldc_stamp(&P.sr[e1]);
   if (removed_at(rnd1, r)) return;
   int32_t e2;
-  if (P.probe == 0) {
+  if (probe == 0) {
     e2 = edge_lookup(P.etab, P.etab_mask, b, w);
     if (e2 < 0) return;
   } else {
@@ -453,7 +535,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
   __shared__ int s_tmp[kWaves + 2];
   __shared__ int s_c0;
   __shared__ unsigned long long s_pv;
-  __shared__ int s_inl;
+  __shared__ unsigned long long s_w64[kWaves];
   PeelCtl* c = P.ctl;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -495,6 +577,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       const int32_t* A = P.alist[acur];
       const int stamp = phase == PH_START ? r : r + 1;
       int32_t* Q = P.fq[stamp & 1];
+      unsigned long long wsum = 0;  // level start: shorter live row over the frontier
       for (int64_t base = (int64_t)blockIdx.x * kT; base < cnt; base += (int64_t)gridDim.x * kT) {
         const int64_t i = base + tid;
         bool take = false;
@@ -506,14 +589,29 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
           if (take) {
             stc_stamp(&P.sr[e], stamp);
             P.truss[e] = k;
+            if (phase == PH_START) {
+              const int du = P.rlen[P.eu[e]], dv = P.rlen[P.ev[e]];
+              wsum += (unsigned long long)(du < dv ? du : dv);
+            }
           }
         }
         const int pos = block_append(&c->w_qlen, take, s_tmp);
         if (take) stc(&Q[pos], e);
       }
+      if (phase == PH_START) {
+        wsum = wave_sum(wsum);
+        if (lane == 0) s_w64[wv] = wsum;
+        __syncthreads();
+        if (tid == 0) {
+          unsigned long long t = 0;
+          for (int q = 0; q < kWaves; ++q) t += s_w64[q];
+          if (t) atomicAdd(&c->w_fwork, t);
+        }
+      }
     } else if (phase == PH_PROC) {
       const int qn = ldc(&c->qlen);
       const bool sparse = ldc(&c->mode) == TRUSS_PEEL_SPARSE;
+      const int probe = ldc(&c->probe);
       const int32_t* Q = P.fq[r & 1];
       WaveQueue wq{s_wq[wv], 0, P.fq[(r + 1) & 1], &c->w_qlen};
       const unsigned long long cap = (unsigned long long)ldc(&c->pcap);
@@ -529,7 +627,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
               const int mid = (x + y + 1) >> 1;
               if (s_pre[mid] <= t) x = mid; else y = mid - 1;
             }
-            process_entry(P, s_e[x], s_b[x], s_base[x] + (t - s_pre[x]), r, l, k, sparse, f1, f2);
+            process_entry(P, s_e[x], s_b[x], s_base[x] + (t - s_pre[x]), r, l, k, sparse, probe, f1, f2);
           }
           wq_push(wq, f1, f2);
         }
@@ -674,7 +772,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       }
       wq_flush(wq);
     }
-    if (!phase_barrier(c)) break;
+    if (!phase_barrier(c, P)) break;
   }
   if (tid == 0 && my_work) atomicAdd(&c->w_work, my_work);
 }
@@ -716,7 +814,7 @@ __global__ void __launch_bounds__(256) k_compact(const int64_t* __restrict__ row
 }
 
 __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int32_t* __restrict__ rlen, int32_t n,
-                            int64_t m, long long max_subrounds, int force_mode, int pcap,
+                            int64_t m, long long max_subrounds, int sched, int fix_bits, int fix_vals, int pcap,
                             unsigned long long* __restrict__ pslot) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) rlen[i] = (int32_t)(row_ptr[i + 1] - row_ptr[i]);
@@ -733,6 +831,7 @@ __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int
     c->w_chunks = 0;
     c->w_pieces = 0ULL;
     c->w_work = 0ULL;
+    c->w_fwork = 0ULL;
     c->phase = PH_SWEEP;
     c->k = 1;
     c->r = 0;
@@ -754,8 +853,15 @@ __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int
     for (int b = 0; b < 8; ++b) c->t_phase[b] = 0;
     c->err = 0;
     c->abort = 0;
-    c->force_mode = force_mode;
     c->launches = 0;
+    c->probe = 0;
+    c->sched = sched;
+    c->fix_bits = fix_bits;
+    c->fix_vals = fix_vals;
+    c->m_edges = (int)m;
+    c->lvl_sub0 = 0;
+    c->prev_sub = 0;
+    c->t_dec = 0;
   }
 }
 
@@ -795,19 +901,18 @@ size_t peel_workspace(const DevGraph& dg, Arena& a) {
   return a.used;
 }
 
-int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss_canon, Arena& a, PeelResult* res,
-         hipStream_t s) {
+int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_canon, Arena& a, PeelResult* res,
+         hipStream_t s, truss_trace* trace) {
   PeelLayout L;
   carve(dg, a, L);
   if (a.overflow()) return TRUSS_E_WORKSPACE;
   *res = PeelResult();
   if (dg.m == 0) return TRUSS_OK;
-  const int force = opts ? opts->peel_mode : TRUSS_PEEL_AUTO;
-  const long long maxsr = opts ? opts->max_subrounds : 0;
+  const long long maxsr = plan.max_subrounds;
   int64_t initn = dg.n > L.pcap ? dg.n : L.pcap;
   if (initn < 1) initn = 1;
   hipLaunchKernelGGL(k_peel_init, dim3((unsigned)((initn + 255) / 256)), dim3(256), 0, s, L.ctl, dg.row_ptr, L.rlen,
-                     dg.n, dg.m, maxsr, force, L.pcap, L.pslot);
+                     dg.n, dg.m, maxsr, plan.sched, plan.fix_bits, plan.fix_vals, L.pcap, L.pslot);
   if (g_peel_blocks == 0) {
     int dev = 0, cus = 0, occ = 0;
     TRUSS_HIP(hipGetDevice(&dev));
@@ -820,7 +925,7 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
     g_peel_blocks = cus;  // one workgroup per compute unit
   }
   int blocks = g_peel_blocks;
-  if (opts && opts->grid_blocks > 0 && opts->grid_blocks < blocks) blocks = opts->grid_blocks;
+  if (plan.grid_blocks > 0 && plan.grid_blocks < blocks) blocks = plan.grid_blocks;
   PeelArgs P;
   P.n = dg.n;
   P.m = dg.m;
@@ -844,8 +949,12 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
   P.rec_tot = L.rec_tot;
   P.etab = dg.etab;
   P.etab_mask = dg.etab_mask;
-  P.probe = (opts && opts->peel_probe == TRUSS_PROBE_BSEARCH) ? 1 : 0;
   P.ctl = L.ctl;
+  P.model = plan.sched == TRUSS_SCHED_LEARNED ? plan.model : nullptr;
+  P.tr_cap = trace && trace->level_feat && trace->level_ms && trace->level_action ? trace->level_cap : 0;
+  P.tr_feat = P.tr_cap > 0 ? trace->level_feat : nullptr;
+  P.tr_ms = P.tr_cap > 0 ? trace->level_ms : nullptr;
+  P.tr_act = P.tr_cap > 0 ? trace->level_action : nullptr;
   void* args[] = {&P};
   PeelCtl h;
   int launches = 0;
@@ -869,6 +978,7 @@ int peel(const DevGraph& dg, const truss_options* opts, int2* sr, int32_t* truss
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   res->kernel_ms = kernel_ms;
+  if (trace) trace->levels = h.levels < P.tr_cap ? h.levels : P.tr_cap;
   res->kmax = h.kmax;
   res->levels = h.levels;
   res->subrounds = h.subrounds;

@@ -12,12 +12,14 @@
 // Work decomposition: vertices with |N+(a)| >= 2 are binned by |N+(a)|; a
 // wavefront owns a vertex of the small bin, a workgroup one of the larger bins.
 // The (b, c) pairs of a vertex are flattened (prefix sums over |N+(b)|) so the
-// lanes stay busy whatever the individual out-degrees are.  Membership of c in
-// N+(a) is an LDS hash probe (TRUSS_SUP_HASH) or a binary search of N+(a) in
-// global memory (TRUSS_SUP_BSEARCH).  TRUSS_SUP_MERGE uses one lane per
-// oriented edge and merges N+(a) with N+(b).
+// lanes stay busy whatever the individual out-degrees are.  Each bin takes one
+// of three intersection methods, chosen per bin on the device (k_sup_decide):
+// membership of c in N+(a) by an LDS hash probe, by a binary search of N+(a)
+// in global memory, or a merge of N+(a) with N+(b), one lane per oriented edge
+// a -> b.  The kernels of the methods not chosen exit at once.
 #include "common.hpp"
 #include "internal.hpp"
+#include "mlp.hpp"
 
 namespace truss {
 
@@ -30,35 +32,118 @@ constexpr int kBlockMax1 = 1024; // bin 1: d <= 1024, a workgroup per vertex
 constexpr int kBlockMax2 = 4096; // bin 2: d <= 4096, a workgroup per vertex
                                  // bin 3: larger, chunked binary search
 
-enum { kHash = 0, kBsearch = 1 };
+static_assert(kBins == kSupBins, "support bins");
+
+// bin actions (the scheduler's support outputs)
+enum { kHash = 0, kBsearch = 1, kMerge = 2 };
 
 __device__ __forceinline__ uint32_t hslot(int32_t c, int logsz) {
   return ((uint32_t)c * 2654435769u) >> (32 - logsz);
 }
 
 struct SupCtl {
-  int cnt[kBins];
-  int fetch[kBins];
+  int cnt[kBins];    // vertices per bin
+  int fetch[kBins];  // next vertex of the bin to take
+  int act[kBins];    // method chosen for the bin
+  unsigned long long sd[kBins], sd2[kBins];  // sum of d+ and of d+^2 over the bin
+  float feat[kBins][kSupF];                  // the decision's features
 };
 
 __global__ void k_sup_zero(int2* __restrict__ sr, int64_t m, SupCtl* ctl) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < m) sr[i] = make_int2(0, 0);
-  if (i < kBins) { ctl->cnt[i] = 0; ctl->fetch[i] = 0; }
+  if (i < kBins) {
+    ctl->cnt[i] = 0;
+    ctl->fetch[i] = 0;
+    ctl->act[i] = 0;
+    ctl->sd[i] = 0ULL;
+    ctl->sd2[i] = 0ULL;
+  }
 }
 
-__global__ void k_sup_bin(const int64_t* __restrict__ orow, int32_t n, int32_t* __restrict__ vlist, SupCtl* ctl,
-                          int all_bsearch) {
-  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Bins the vertices by d+ = |N+(a)| and sums d+ and d+^2 per bin; counts are
+// gathered per wavefront, then per workgroup, so each bin counter sees one
+// atomic per workgroup.
+constexpr int kBinT = 1024;
+__global__ void __launch_bounds__(kBinT) k_sup_bin(const int64_t* __restrict__ orow, int32_t n,
+                                                   int32_t* __restrict__ vlist, SupCtl* ctl) {
+  __shared__ int s_c[kBins], s_base[kBins];
+  __shared__ unsigned long long s_d[kBins], s_d2[kBins];
+  if (threadIdx.x < kBins) {
+    s_c[threadIdx.x] = 0;
+    s_d[threadIdx.x] = 0ULL;
+    s_d2[threadIdx.x] = 0ULL;
+  }
+  __syncthreads();
+  const int64_t a = blockIdx.x * (int64_t)kBinT + threadIdx.x;
   int d = 0;
   if (a < n) d = (int)(orow[a + 1] - orow[a]);
   int bin = -1;
   if (d >= 2) bin = d <= kWaveMax ? 0 : d <= kBlockMax1 ? 1 : d <= kBlockMax2 ? 2 : 3;
-  if (all_bsearch && bin > 0) bin = 3;
+  int local = 0;
+  const int lane = lane_id();
 #pragma unroll
   for (int q = 0; q < kBins; ++q) {
-    int pos = wave_append(&ctl->cnt[q], bin == q);
-    if (bin == q) vlist[(int64_t)q * n + pos] = (int32_t)a;
+    const uint64_t msk = ballot(bin == q);
+    if (msk == 0) continue;
+    const unsigned long long x = bin == q ? (unsigned long long)d : 0ULL;
+    const unsigned long long sd = wave_sum(x), sd2 = wave_sum(x * x);
+    const int leader = __builtin_ctzll(msk);
+    int wb = 0;
+    if (lane == leader) {
+      wb = atomicAdd(&s_c[q], __popcll(msk));
+      atomicAdd(&s_d[q], sd);
+      atomicAdd(&s_d2[q], sd2);
+    }
+    wb = __shfl(wb, leader, kWave);
+    if (bin == q) local = wb + rank_below(msk);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins) {
+    const int q = threadIdx.x;
+    if (s_c[q] > 0) {
+      s_base[q] = atomicAdd(&ctl->cnt[q], s_c[q]);
+      atomicAdd(&ctl->sd[q], s_d[q]);
+      atomicAdd(&ctl->sd2[q], s_d2[q]);
+    }
+  }
+  __syncthreads();
+  if (bin >= 0) vlist[(int64_t)bin * n + s_base[bin] + local] = (int32_t)a;
+}
+
+// One wavefront per bin picks the bin's method.  force >= 0: that method for
+// every bin (hash becomes binary search in the last bin); otherwise by
+// scheduler: plain = merge; heuristic = hash, binary search in the last bin;
+// learned = the allowed method with the smallest model score.
+__global__ void __launch_bounds__(kBins * kWave) k_sup_decide(SupCtl* ctl, int64_t m, int sched, int force,
+                                                               const float* __restrict__ model) {
+  const int b = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const float cnt = (float)ctl->cnt[b];
+  const float sd = (float)ctl->sd[b], sd2 = (float)ctl->sd2[b];
+  float x[kSupF];
+  x[0] = log2f(1.f + cnt);
+  x[1] = log2f(1.f + sd);
+  x[2] = log2f(1.f + sd2);
+  x[3] = log2f(1.f + sd / (cnt > 1.f ? cnt : 1.f));
+  x[4] = log2f(1.f + (float)m);
+  x[5] = log2f(1.f + sd2 / (sd > 1.f ? sd : 1.f));
+  const unsigned allowed = b == kBins - 1 ? 0x6u : 0x7u;
+  int act;
+  if (force >= 0) {
+    act = (force == kHash && b == kBins - 1) ? kBsearch : force;
+  } else if (sched == TRUSS_SCHED_PLAIN) {
+    act = kMerge;
+  } else if (sched == TRUSS_SCHED_LEARNED && model != nullptr) {
+    float sc[kSupA];
+    mlp_scores_wave(model, x, sc);
+    act = argmin_allowed(sc, kSupA, allowed);
+  } else {
+    act = b == kBins - 1 ? kBsearch : kHash;
+  }
+  if (lane == 0) {
+    ctl->act[b] = act;
+    for (int i = 0; i < kSupF; ++i) ctl->feat[b][i] = x[i];
   }
 }
 
@@ -76,6 +161,7 @@ __global__ void __launch_bounds__(kT) k_sup_wave(const int64_t* __restrict__ oro
   __shared__ int s_pre[W][kWaveMax + 1];
   __shared__ int64_t s_off[W][kWaveMax];
   __shared__ int s_tab[W][2 * kWaveMax];
+  if (ctl->act[0] != MODE) return;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int count = atomic_load_relaxed(&ctl->cnt[0]);
   for (;;) {
@@ -164,6 +250,7 @@ __global__ void __launch_bounds__(kT) k_sup_block(const int64_t* __restrict__ or
   __shared__ int s_tab[MODE == kHash ? TAB : 1];
   __shared__ int s_wt[kT / kWave];
   __shared__ int s_idx;
+  if (ctl->act[bin] != MODE) return;
   const int count = atomic_load_relaxed(&ctl->cnt[bin]);
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(&ctl->fetch[bin], 1);
@@ -250,24 +337,26 @@ __global__ void __launch_bounds__(kT) k_sup_block(const int64_t* __restrict__ or
   }
 }
 
-// ---- bin 3: a workgroup per vertex, N+(a) searched in global memory, chunks of 256 b's --------
+// ---- bins 1-3, binary search: a workgroup per vertex, N+(a) searched in global memory,
+// chunks of 256 b's ------------------------------------------------------------------------
 __global__ void __launch_bounds__(kT) k_sup_chunked(const int64_t* __restrict__ orow, const int32_t* __restrict__ ocol,
                                                     const int32_t* __restrict__ oeid, int32_t n,
-                                                    const int32_t* __restrict__ vlist, SupCtl* ctl,
+                                                    const int32_t* __restrict__ vlist, int bin, SupCtl* ctl,
                                                     int2* __restrict__ sr) {
   __shared__ int s_cnt[kT];
   __shared__ int s_pre[kT + 1];
   __shared__ int64_t s_off[kT];
   __shared__ int s_wt[kT / kWave];
   __shared__ int s_idx;
-  const int count = atomic_load_relaxed(&ctl->cnt[3]);
+  if (ctl->act[bin] != kBsearch) return;
+  const int count = atomic_load_relaxed(&ctl->cnt[bin]);
   for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(&ctl->fetch[3], 1);
+    if (threadIdx.x == 0) s_idx = atomicAdd(&ctl->fetch[bin], 1);
     __syncthreads();
     const int idx = s_idx;
     __syncthreads();
     if (idx >= count) break;
-    const int32_t a = vlist[(int64_t)3 * n + idx];
+    const int32_t a = vlist[(int64_t)bin * n + idx];
     const int64_t base = orow[a];
     const int d = (int)(orow[a + 1] - base);
     for (int c0 = 0; c0 < d; c0 += kT) {
@@ -317,30 +406,46 @@ __global__ void __launch_bounds__(kT) k_sup_chunked(const int64_t* __restrict__ 
   }
 }
 
-// ---- merge: one lane per oriented edge a->b, two-pointer merge of N+(a) and N+(b) ------------
-__global__ void __launch_bounds__(kT) k_sup_merge(const int64_t* __restrict__ row_ptr,
-                                                  const int64_t* __restrict__ orow, const int32_t* __restrict__ ocol,
-                                                  const int32_t* __restrict__ oeid, const int32_t* __restrict__ eu,
-                                                  const int32_t* __restrict__ ev, int64_t m, int2* __restrict__ sr) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  const int32_t u = eu[e], v = ev[e];
-  const bool ub = vertex_before(row_ptr[u + 1] - row_ptr[u], u, row_ptr[v + 1] - row_ptr[v], v);
-  const int32_t a = ub ? u : v, b = ub ? v : u;
-  int64_t i = orow[a], ie = orow[a + 1], j = orow[b], je = orow[b + 1];
-  int cnt = 0;
-  while (i < ie && j < je) {
-    const int32_t ci = ocol[i], cj = ocol[j];
-    if (ci < cj) ++i;
-    else if (ci > cj) ++j;
-    else {
-      ++cnt;
-      atomicAdd(sup_ptr(sr, oeid[i]), 1);
-      atomicAdd(sup_ptr(sr, oeid[j]), 1);
-      ++i; ++j;
+// ---- merge: a wavefront per vertex a of the bin, one lane per oriented edge a -> b,
+// two-pointer merge of N+(a) and N+(b) ---------------------------------------------------------
+__global__ void __launch_bounds__(kT) k_sup_merge(const int64_t* __restrict__ orow, const int32_t* __restrict__ ocol,
+                                                  const int32_t* __restrict__ oeid, int32_t n,
+                                                  const int32_t* __restrict__ vlist, int bin, SupCtl* ctl,
+                                                  int2* __restrict__ sr) {
+  if (ctl->act[bin] != kMerge) return;
+  const int lane = lane_id();
+  const int count = atomic_load_relaxed(&ctl->cnt[bin]);
+  for (;;) {
+    int idx = 0;
+    if (lane == 0) idx = atomicAdd(&ctl->fetch[bin], 1);
+    idx = __shfl(idx, 0, kWave);
+    if (idx >= count) break;
+    const int32_t a = vlist[(int64_t)bin * n + idx];
+    const int64_t base = orow[a], end = orow[a + 1];
+    for (int64_t e0 = base; e0 < end; e0 += kWave) {
+      const int64_t i = e0 + lane;
+      if (i >= end) continue;
+      const int32_t b = ocol[i];
+      int64_t p = base, q = orow[b];
+      const int64_t qe = orow[b + 1];
+      int cnt = 0;
+      while (p < end && q < qe) {
+        const int32_t cp = ocol[p], cq = ocol[q];
+        if (cp < cq) {
+          ++p;
+        } else if (cp > cq) {
+          ++q;
+        } else {
+          ++cnt;
+          atomicAdd(sup_ptr(sr, oeid[p]), 1);
+          atomicAdd(sup_ptr(sr, oeid[q]), 1);
+          ++p;
+          ++q;
+        }
+      }
+      if (cnt) atomicAdd(sup_ptr(sr, oeid[i]), cnt);
     }
   }
-  if (cnt) atomicAdd(sup_ptr(sr, (int32_t)e), cnt);
 }
 
 inline unsigned grid_for(int64_t n) {
@@ -366,7 +471,8 @@ size_t support_workspace(const DevGraph& dg, Arena& a) {
   return a.used;
 }
 
-int compute_support(const DevGraph& dg, int strategy, int2* sr, Arena& a, hipStream_t s) {
+int compute_support(const DevGraph& dg, const SupPlan& plan, int2* sr, Arena& a, hipStream_t s,
+                    truss_trace* trace) {
   SupLayout L;
   carve(dg, a, L);
   if (a.overflow()) return TRUSS_E_WORKSPACE;
@@ -374,28 +480,52 @@ int compute_support(const DevGraph& dg, int strategy, int2* sr, Arena& a, hipStr
   const int32_t n = dg.n;
   hipLaunchKernelGGL(k_sup_zero, dim3(grid_for(m > kBins ? m : kBins)), dim3(kT), 0, s, sr, m, L.ctl);
   if (m == 0) return TRUSS_OK;
-  if (strategy == TRUSS_SUP_MERGE) {
-    hipLaunchKernelGGL(k_sup_merge, dim3(grid_for(m)), dim3(kT), 0, s, dg.row_ptr, dg.orow, dg.ocol, dg.oeid, dg.eu, dg.ev, m,
-                       sr);
-    TRUSS_HIP(hipGetLastError());
-    return TRUSS_OK;
-  }
-  const bool bs = strategy == TRUSS_SUP_BSEARCH;
-  hipLaunchKernelGGL(k_sup_bin, dim3(grid_for(n)), dim3(kT), 0, s, dg.orow, n, L.vlist, L.ctl, bs ? 1 : 0);
+  hipLaunchKernelGGL(k_sup_bin, dim3((unsigned)((n + kBinT - 1) / kBinT > 0 ? (n + kBinT - 1) / kBinT : 1)),
+                     dim3(kBinT), 0, s, dg.orow, n, L.vlist, L.ctl);
+  hipLaunchKernelGGL(k_sup_decide, dim3(1), dim3(kBins * kWave), 0, s, L.ctl, m, plan.sched, plan.force,
+                     plan.model);
+  hipEvent_t ev[kBins + 1] = {};
+  bool timed = trace != nullptr;
+  for (int b = 0; timed && b <= kBins; ++b)
+    if (hipEventCreate(&ev[b]) != hipSuccess) timed = false;
   // persistent-style grids: workers fetch vertices from the bin lists
-  const unsigned gw = 256 * 8, gb = 256 * 4;
-  if (bs) {
-    hipLaunchKernelGGL(k_sup_wave<kBsearch>, dim3(gw), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n, L.vlist, L.ctl,
-                       sr);
-  } else {
-    hipLaunchKernelGGL(k_sup_wave<kHash>, dim3(gw), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n, L.vlist, L.ctl, sr);
-    hipLaunchKernelGGL((k_sup_block<kHash, kBlockMax1>), dim3(gb), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n,
-                       L.vlist, 1, L.ctl, sr);
-    hipLaunchKernelGGL((k_sup_block<kHash, kBlockMax2>), dim3(256), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n,
-                       L.vlist, 2, L.ctl, sr);
+  const unsigned gw = 256 * 8, gb = 256 * 4, g2 = 256;
+  for (int b = 0; b < kBins; ++b) {
+    if (timed) (void)hipEventRecord(ev[b], s);
+    if (b == 0) {
+      hipLaunchKernelGGL(k_sup_wave<kHash>, dim3(gw), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n, L.vlist, L.ctl,
+                         sr);
+      hipLaunchKernelGGL(k_sup_wave<kBsearch>, dim3(gw), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n, L.vlist,
+                         L.ctl, sr);
+    } else if (b == 1) {
+      hipLaunchKernelGGL((k_sup_block<kHash, kBlockMax1>), dim3(gb), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n,
+                         L.vlist, 1, L.ctl, sr);
+    } else if (b == 2) {
+      hipLaunchKernelGGL((k_sup_block<kHash, kBlockMax2>), dim3(g2), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n,
+                         L.vlist, 2, L.ctl, sr);
+    }
+    if (b > 0)
+      hipLaunchKernelGGL(k_sup_chunked, dim3(b == 1 ? gb : g2), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n,
+                         L.vlist, b, L.ctl, sr);
+    hipLaunchKernelGGL(k_sup_merge, dim3(b == 0 ? gw : gb), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n, L.vlist,
+                       b, L.ctl, sr);
   }
-  hipLaunchKernelGGL(k_sup_chunked, dim3(256), dim3(kT), 0, s, dg.orow, dg.ocol, dg.oeid, n, L.vlist, L.ctl, sr);
+  if (timed) (void)hipEventRecord(ev[kBins], s);
   TRUSS_HIP(hipGetLastError());
+  if (trace) {
+    SupCtl h;
+    TRUSS_HIP(hipMemcpyAsync(&h, L.ctl, sizeof(SupCtl), hipMemcpyDeviceToHost, s));
+    TRUSS_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < kBins; ++b) {
+      trace->sup_action[b] = h.act[b];
+      for (int i = 0; i < kSupF; ++i) trace->sup_feat[b][i] = h.feat[b][i];
+      float t = 0.f;
+      if (timed && hipEventElapsedTime(&t, ev[b], ev[b + 1]) != hipSuccess) t = 0.f;
+      trace->sup_ms[b] = t;
+    }
+  }
+  for (int b = 0; b <= kBins; ++b)
+    if (ev[b]) (void)hipEventDestroy(ev[b]);
   return TRUSS_OK;
 }
 

@@ -1,0 +1,65 @@
+"""Writes the stored expected values of the full-size parity tests.
+
+Calls only the CPU oracle (oracle/) on seeded synthetic inputs (graphgen/), never
+the GPU library.  Each output file records, for one workload, the oracle's
+truss numbers and supports in canonical edge order (u < v, sorted by (u, v),
+which is also the library's CSR output order) as SHA-256 digests of the int32
+arrays, the triangle count, k_max and the size of every k-class.
+
+Usage: python tests/golden/make_golden.py rmat20      (about 5 minutes, one core)
+       python tests/golden/make_golden.py chunglu4m   (the 57M-edge Chung-Lu graph; about 8 minutes)
+       python tests/golden/make_golden.py rmat24      (260M edges; hours, about 30 GB of RAM)
+"""
+import hashlib
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+
+WORKLOADS = {
+    "rmat20": lambda: graphgen.rmat20(1),
+    "er2000": lambda: graphgen.er_small(1),
+    "rmat16": lambda: graphgen.rmat(16, 16, 1),
+    "chunglu4m": lambda: graphgen.chung_lu4m(1),
+    "rmat24": lambda: graphgen.rmat24(1),
+}
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+
+
+def main(name):
+    n, s, d = WORKLOADS[name]()
+    t0 = time.time()
+    sup, tri = oracle.support_fwd(n, s, d)
+    phi, kmax = oracle.truss(n, s, d)
+    hist = np.bincount(phi, minlength=kmax + 1)
+    lines = [
+        "# Oracle results for workload %s (seed 1), canonical edge order." % name,
+        "# Written by tests/golden/make_golden.py from oracle.support_fwd and oracle.truss",
+        "# (%.0f s on one core)." % (time.time() - t0),
+        "n: %d" % n,
+        "m: %d" % s.size,
+        "triangles: %d" % tri,
+        "kmax: %d" % kmax,
+        "truss_sha256: %s" % digest(phi),
+        "support_sha256: %s" % digest(sup),
+        "class_sizes: %s" % " ".join("%d:%d" % (k, c) for k, c in enumerate(hist) if c),
+    ]
+    path = os.path.join(HERE, "oracle_%s.txt" % name)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "rmat20")

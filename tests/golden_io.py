@@ -45,3 +45,31 @@ def edge_index(src, dst, u, v):
         if {int(src[i]), int(dst[i])} == {u, v}:
             return i
     raise KeyError((u, v))
+
+
+def oracle_record(name):
+    """Fields of tests/golden/oracle_<name>.txt (written by make_golden.py), or
+    None if the file has not been generated."""
+    path = os.path.join(GOLDEN, "oracle_%s.txt" % name)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, val = line.split(":", 1)
+            val = val.strip()
+            if key in ("n", "m", "triangles", "kmax"):
+                rec[key] = int(val)
+            elif key == "class_sizes":
+                rec[key] = {int(a): int(b) for a, b in (t.split(":") for t in val.split())}
+            else:
+                rec[key] = val
+    return rec
+
+
+def int32_digest(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()

@@ -1,0 +1,52 @@
+"""Full-size parity: the HIP path at the workload sizes the benchmark times,
+against the oracle's results stored in tests/golden/oracle_<name>.txt (written
+by tests/golden/make_golden.py, which calls only the oracle).
+
+Outputs of a CSR input are in canonical edge order (u < v, sorted by (u, v)),
+the order the generators emit and the digests are taken in, so the comparison
+is bit-exact over every edge: SHA-256 of the int32 truss and support arrays,
+plus the triangle count, k_max and the size of every k-class (which localise a
+mismatch).
+"""
+import numpy as np
+import pytest
+
+import golden_io
+import graphgen
+from gpu_util import csr_graph, gpu_support, gpu_truss, say
+
+pytestmark = pytest.mark.gpu
+
+WORKLOADS = {
+    "er2000": lambda: graphgen.er_small(1),
+    "rmat16": lambda: graphgen.rmat(16, 16, 1),
+    "rmat20": lambda: graphgen.rmat20(1),
+    "chunglu4m": lambda: graphgen.chung_lu4m(1),
+}
+
+# scheduler 0 = plain (merge support, dense frontier, bsearch probes),
+# 1 = fixed heuristic (the default)
+SCHEDULERS = [dict(), dict(scheduler=0)]
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_fullsize_digest(name):
+    rec = golden_io.oracle_record(name)
+    if rec is None:
+        pytest.skip("oracle record for %s not generated" % name)
+    say(f"case: full-size {name}")
+    n, s, d = WORKLOADS[name]()
+    assert n == rec["n"] and s.size == rec["m"]
+    assert np.all(s < d) and np.all(np.diff(s.astype(np.int64) * n + d) > 0)  # canonical order
+    g = csr_graph(n, s, d)
+    sup, tri = gpu_support(g)
+    assert tri == rec["triangles"]
+    assert golden_io.int32_digest(sup) == rec["support_sha256"]
+    for opt in SCHEDULERS:
+        say(f"  options {opt}")
+        phi, st = gpu_truss(g, **opt)
+        hist = np.bincount(phi, minlength=rec["kmax"] + 1)
+        got = {k: int(c) for k, c in enumerate(hist) if c}
+        assert st["kmax"] == rec["kmax"]
+        assert got == rec["class_sizes"]
+        assert golden_io.int32_digest(phi) == rec["truss_sha256"]

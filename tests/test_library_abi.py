@@ -102,3 +102,35 @@ def test_batch_workspace_is_max_over_graphs(T):
     b = ctypes.c_size_t(0)
     assert lib.truss_workspace_size(ctypes.byref(_graph(T, 20, 180)), None, ctypes.byref(b)) == 0
     assert sz == b.value
+
+
+def test_trace_layout_and_network_sizes(T):
+    # trace: 2 ints, 3 pointers, 4 actions, 4 x 6 features, 4 times
+    assert ctypes.sizeof(T.Trace) == 8 + 24 + 16 + 96 + 16
+    lib = T.load_library()
+    assert T.mlp_param_count(8, 32, 4) == 32 * 8 + 32 + 4 * 32 + 4
+    assert lib.truss_mlp_param_count(0, 4, 4) == T.E_INVAL
+    assert lib.truss_mlp_param_count(17, 4, 4) == T.E_INVAL
+    assert lib.truss_mlp_param_count(8, 65, 4) == T.E_INVAL
+    assert lib.truss_mlp_param_count(8, 4, 9) == T.E_INVAL
+    # a model part: header, normalisation, parameters
+    assert T.sched_part_floats(0, 32) == 4 + 2 * 8 + T.mlp_param_count(8, 32, 4)
+    assert T.sched_part_floats(1, 16) == 4 + 2 * 6 + T.mlp_param_count(6, 16, 3)
+    assert lib.truss_sched_model_floats(32) == T.sched_part_floats(0, 32) + T.sched_part_floats(1, 32)
+    assert lib.truss_sched_part_floats(2, 32) == T.E_INVAL
+    b = ctypes.c_size_t(0)
+    assert lib.truss_mlp_workspace_size(8, 32, 4, 1000, ctypes.byref(b)) == 0 and b.value > 1000 * 32 * 4
+    assert lib.truss_mlp_workspace_size(8, 32, 4, 0, ctypes.byref(b)) == T.E_INVAL
+    assert lib.truss_sched_train_workspace_size(0, 32, 100, ctypes.byref(b)) == 0
+    # host-side argument checks of the network entry points
+    assert lib.truss_mlp_forward(None, 8, 32, 4, None, 10, None, None, 0, None) == T.E_INVAL
+    p = ctypes.c_void_p(4096)
+    assert lib.truss_mlp_forward(p, 8, 32, 4, p, 10, p, None, 0, None) == T.E_WORKSPACE
+    assert lib.truss_mlp_train(p, p, p, 8, 32, 4, p, p, p, 10, 5, 0, ctypes.c_float(0.0), None, None, 0,
+                               None) == T.E_INVAL
+    tr = T.Trace()
+    g = _graph(T, 5, 5)
+    assert lib.truss_decompose_traced(ctypes.byref(g), p, None, None, None, None, 0, None) == T.E_INVAL
+    tr.level_cap = 4
+    assert lib.truss_decompose_traced(ctypes.byref(g), p, None, None, ctypes.byref(tr), None, 0,
+                                      None) == T.E_WORKSPACE

@@ -246,3 +246,22 @@ def test_csr_to_edges_canonical_order():
     s2, d2 = oracle.csr_to_edges(n, s.size, rp, col)
     np.testing.assert_array_equal(s2, s)
     np.testing.assert_array_equal(d2, d)
+
+
+@pytest.mark.parametrize("name", ["er2000", "rmat16"])
+def test_stored_oracle_records(name):
+    """The stored full-size records (tests/golden/oracle_<name>.txt) are what
+    the oracle computes today: the generator output is canonical and the
+    digests, triangle count and class sizes match a fresh oracle run."""
+    import golden_io
+    rec = golden_io.oracle_record(name)
+    assert rec is not None
+    n, s, d = graphgen.er_small(1) if name == "er2000" else graphgen.rmat(16, 16, 1)
+    assert n == rec["n"] and s.size == rec["m"]
+    sup, tri = oracle.support_fwd(n, s, d)
+    phi, kmax = oracle.truss(n, s, d)
+    assert tri == rec["triangles"] and kmax == rec["kmax"]
+    assert golden_io.int32_digest(sup) == rec["support_sha256"]
+    assert golden_io.int32_digest(phi) == rec["truss_sha256"]
+    hist = np.bincount(phi)
+    assert {k: int(c) for k, c in enumerate(hist) if c} == rec["class_sizes"]
