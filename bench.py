@@ -1,10 +1,12 @@
 #!/usr/bin/env python3
-"""Benchmark: truss-decomposed edges/s on one MI355X.
+"""Benchmark: truss-decomposed edges/s on one MI355X, plain vs learned-scheduled.
 
 A step is one truss_decompose call on the resident input graph: validation,
 CSR build, support counting, peeling, output.  Inputs are generated on the host
 from a seed and copied to HBM before the timed region; the timed region covers
-exactly K steps bracketed by device synchronisation.
+exactly K steps bracketed by device synchronisation.  The headline value is the
+learned-scheduled form (the committed model); the plain and heuristic forms
+are timed the same way afterwards for comparison.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (measured with HIP events on the library's stream) and the CPU oracle timed on a
@@ -150,7 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--scheduler", default="heuristic", choices=["plain", "heuristic", "learned"])
+    ap.add_argument("--scheduler", default="learned", choices=["plain", "heuristic", "learned"])
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the other scheduler forms")
     ap.add_argument("--probe", default="auto", choices=["auto", "hash", "bsearch"])
     ap.add_argument("--peel-mode", default="auto", choices=["auto", "sparse", "dense"])
     ap.add_argument("--support", default="auto", choices=["auto", "hash", "bsearch", "merge"])
@@ -189,11 +192,19 @@ def main():
         g = T.Graph.from_edges(n, torch.from_numpy(s2).cuda(), torch.from_numpy(d2).cuda())
         row_ptr, col = graphgen.to_csr(n, s, d)
         model = host_work_model(n, row_ptr, col)
-    sched = {"plain": T.SCHED_PLAIN, "heuristic": T.SCHED_HEURISTIC, "learned": T.SCHED_LEARNED}[args.scheduler]
-    opts = T.make_options(scheduler=sched,
-                          peel_probe={"auto": 0, "hash": 1, "bsearch": 2}[args.probe],
-                          peel_mode={"auto": 0, "sparse": 1, "dense": 2}[args.peel_mode],
-                          support_strategy={"auto": 0, "hash": 1, "bsearch": 2, "merge": 3}[args.support])
+    sched_ids = {"plain": T.SCHED_PLAIN, "heuristic": T.SCHED_HEURISTIC, "learned": T.SCHED_LEARNED}
+    from paper_1205_6693_amd import sched as S
+    sched_model = S.load_model() if os.path.exists(S.MODEL_PATH) else None
+
+    def form_options(name):
+        if name == "learned" and sched_model is None:
+            raise SystemExit("learned scheduler requested but %s is missing" % S.MODEL_PATH)
+        return T.make_options(scheduler=sched_ids[name], model=sched_model if name == "learned" else None,
+                              peel_probe={"auto": 0, "hash": 1, "bsearch": 2}[args.probe],
+                              peel_mode={"auto": 0, "sparse": 1, "dense": 2}[args.peel_mode],
+                              support_strategy={"auto": 0, "hash": 1, "bsearch": 2, "merge": 3}[args.support])
+
+    opts = form_options(args.scheduler)
     ws = T.workspace(g, opts)
     out = torch.empty(m, dtype=torch.int32, device="cuda:0")
     torch.cuda.synchronize()
@@ -201,9 +212,11 @@ def main():
 
     for i in range(args.warmup):
         _, st = T.truss_decompose(g, opts, out=out, ws=ws)
-        print("warmup %d: %.2f ms (build %.2f support %.2f peel %.2f) kmax %d subrounds %d"
+        print("warmup %d: %.2f ms (build %.2f support %.2f peel %.2f) kmax %d subrounds %d fallback %d"
               % (i, st["ms_total"], st["ms_build"], st["ms_support"], st["ms_peel"], st["kmax"],
-                 st["subrounds"]), file=sys.stderr, flush=True)
+                 st["subrounds"], st["sched_fallback"]), file=sys.stderr, flush=True)
+        if args.scheduler == "learned" and st["sched_fallback"]:
+            raise SystemExit("the learned model was rejected by the library")
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -239,7 +252,8 @@ def main():
                 "launches_per_step": kd["launches"], "avg_launch_ms": round(kd["ms"] / kd["launches"], 4),
                 "bytes_per_launch": int(kd["bytes"] / kd["launches"])}
     result = {
-        "metric": "truss-decomposed edges/s", "value": m / (ms_per_step * 1e-3), "unit": "edges/s",
+        "metric": "truss-decomposed edges/s + HBM GB/s, plain vs learned-scheduled, 1 MI355X",
+        "value": m / (ms_per_step * 1e-3), "unit": "edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
@@ -256,6 +270,25 @@ def main():
                              "bytes": v["bytes"]} for k, v in kernels.items()},
         "peel_kernel_ms": ms_peel_kernel,
     }
+    forms = {args.scheduler: {"edges_per_s": result["value"], "ms_per_step": ms_per_step}}
+    if not args.no_compare:
+        for name in ("plain", "heuristic", "learned"):
+            if name in forms:
+                continue
+            o = form_options(name)
+            for _ in range(args.warmup):
+                T.truss_decompose(g, o, out=out, ws=ws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                T.truss_decompose(g, o, out=out, ws=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) * 1e3 / args.steps
+            forms[name] = {"edges_per_s": m / (ms * 1e-3), "ms_per_step": ms}
+            print("form %s: %.3f ms/step" % (name, ms), file=sys.stderr, flush=True)
+    result["forms"] = forms
+    if "plain" in forms and "learned" in forms:
+        result["learned_over_plain"] = forms["learned"]["edges_per_s"] / forms["plain"]["edges_per_s"]
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale, args.seed)

@@ -1,9 +1,9 @@
 """Trains the learned scheduler's model file (sched_model.json beside this file).
 
 Training graphs are seeded synthetic graphs (seeds >= 1000) smaller than the
-benchmark workloads: R-MAT (scales 14-19, edge factors 8-32), Chung-Lu
-power-law graphs with planted cliques (up to 2^20 vertices) and Erdos-Renyi
-graphs.  For each, exhaustive timing (sched.exhaustive) records the time of
+benchmark workloads: R-MAT (scales 14-19, edge factors 8-128), Chung-Lu
+power-law graphs with planted cliques (up to 2^20 vertices, cliques up to 4600
+vertices) and Erdos-Renyi graphs.  For each, exhaustive timing (sched.exhaustive) records the time of
 every action at every decision; both model parts are then fitted on the GPU by
 the library's own forward, backward and Adam kernels.  Held-out graphs
 (other seeds and shapes) report the regret of each scheduler against the
@@ -39,6 +39,9 @@ TRAIN = [
     ("cl", 1 << 16, 30, 16, 20, 120, 1010), ("cl", 1 << 18, 30, 32, 30, 250, 1011),
     ("cl", 1 << 19, 20, 32, 40, 300, 1012), ("cl", 1 << 20, 30, 64, 50, 500, 1013),
     ("cl", 1 << 17, 40, 8, 100, 400, 1014),
+    # large planted cliques put vertices in the two high out-degree support bins
+    ("cl", 1 << 16, 20, 4, 1100, 2000, 1015), ("cl", 1 << 17, 20, 1, 4300, 4600, 1016),
+    ("rmat", 15, 128, 1009),
     ("er", 20000, 1e-3, 1020), ("er", 100000, 3e-4, 1021), ("er", 4000, 1e-2, 1022),
 ]
 HELDOUT = [("rmat", 17, 16, 2000), ("cl", 1 << 19, 30, 48, 50, 400, 2001), ("rmat", 19, 12, 2002)]

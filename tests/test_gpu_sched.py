@@ -170,3 +170,39 @@ def test_exhaustive_record_is_consistent():
     for a in range(4):
         assert sched.regret(tab["level_ms"], np.full(L, a)) >= 1.0
     assert sched.regret(tab["level_ms"], np.argmin(tab["level_ms"], axis=1)) == 1.0
+
+
+def test_learned_scheduler_gain():
+    """What the trained network (the committed model file) gains over the
+    method without it, on held-out graphs (seeds and shapes not used in
+    training): the learned form beats the plain form end to end, reaches at
+    least the heuristic's speed within noise, and its per-level choices stay
+    within 10% of the exhaustive per-level best.  Outputs stay bit-exact."""
+    import os
+    from paper_1205_6693_amd import sched, train_sched
+    T = lib()
+    assert os.path.exists(sched.MODEL_PATH), "scheduler model file missing"
+    model = sched.load_model()
+    for spec in [("rmat", 17, 16, 3000), ("cl", 1 << 18, 30, 32, 50, 400, 3001)]:
+        say(f"case: gain on {spec}")
+        n, s, d = train_sched.make_graph(spec)
+        ref, _ = oracle.truss(n, s, d)
+        g = csr_graph(n, s, d)
+        med = {}
+        for name, kw in (("plain", dict(scheduler=T.SCHED_PLAIN)), ("heuristic", dict(scheduler=T.SCHED_HEURISTIC)),
+                         ("learned", dict(scheduler=T.SCHED_LEARNED, model=model))):
+            o = T.make_options(**kw)
+            ts = []
+            for _ in range(7):
+                out, st = T.truss_decompose(g, o)
+                ts.append(st["ms_total"])
+                assert st["sched_fallback"] == 0
+            np.testing.assert_array_equal(out.cpu().numpy(), ref)
+            med[name] = float(np.median(ts[1:]))
+        tab = sched.exhaustive(g, repeats=2)
+        _, _, tr = T.truss_decompose_traced(g, T.make_options(scheduler=T.SCHED_LEARNED, model=model))
+        reg = sched.regret(tab["level_ms"], tr["level_action"])
+        say(f"  median ms {med}; learned per-level regret {reg:.3f}")
+        assert med["learned"] < 0.95 * med["plain"]
+        assert med["learned"] < 1.05 * med["heuristic"]
+        assert reg <= 1.10
