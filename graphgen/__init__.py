@@ -178,14 +178,16 @@ def batch_specs(num_graphs: int, seed: int, n_lo: int = 64, n_hi: int = 8192,
 def batch(num_graphs: int = 4096, seed: int = 1, **kw):
     """Uneven batch: list of (n, src, dst).  Even g: ER with p=min(1, d/(n-1));
     odd g: R-MAT with scale ceil(log2 n), round(n*d/2) samples, ids >= n rejected."""
-    out = []
-    for kind, n, d, s in batch_specs(num_graphs, seed, **kw):
-        if kind == "er":
-            out.append(er(n, min(1.0, d / (n - 1)), s))
-        else:
-            scale = max(1, int(np.ceil(np.log2(n))))
-            out.append(rmat(scale, 0, s, n=n, samples=int(round(n * d / 2))))
-    return out
+    return [batch_graph(spec) for spec in batch_specs(num_graphs, seed, **kw)]
+
+
+def batch_graph(spec):
+    """One graph of the batch from its (kind, n, mean degree, seed) spec."""
+    kind, n, d, s = spec
+    if kind == "er":
+        return er(n, min(1.0, d / (n - 1)), s)
+    scale = max(1, int(np.ceil(np.log2(n))))
+    return rmat(scale, 0, s, n=n, samples=int(round(n * d / 2)))
 
 
 def pack(graphs):

@@ -113,7 +113,9 @@ typedef struct truss_options {
   int64_t max_subrounds;    /* > 0: fail with TRUSS_E_INTERNAL past this many  */
   int32_t grid_blocks;      /* > 0: persistent-kernel workgroups (tuning)      */
   int32_t peel_probe;       /* TRUSS_PROBE_*                                    */
-  int32_t reserved[6];
+  int32_t batch_block;      /* truss_batch: threads per workgroup (256, 512, 1024; 0 = 512) */
+  int32_t batch_lanes;      /* truss_batch: lanes per edge walk (1, 4, 16, 64; 0 = 4)       */
+  int32_t reserved[4];
 } truss_options;
 
 /* Filled when a stats pointer is passed (host). */
@@ -162,18 +164,48 @@ int truss_decompose(const truss_graph *g, int32_t *truss_out, const truss_option
 /* Truss decomposition of many independent graphs at once.
  *   num_graphs  G >= 0.
  *   vtx_off     (host) int64[G+1]: graph g has vertices 0..vtx_off[g+1]-vtx_off[g]-1.
- *   edge_off    (host) int64[G+1]: graph g owns packed edges edge_off[g]..edge_off[g+1]-1.
+ *   edge_off    (host) int64[G+1], edge_off[0] = 0: graph g owns packed edges
+ *               edge_off[g]..edge_off[g+1]-1.
  *   src, dst    (device) int32[edge_off[G]]: graph-local endpoint ids.
  *   truss_out   (device) int32[edge_off[G]]: truss number of each packed edge.
  * Triangles never cross graphs, so the result equals decomposing each graph
- * alone.  Each graph is validated as an edge list; the first failing graph's
- * code is returned. */
+ * alone (Definitions 1-2 per graph).  Graphs with at most 2^21 edges and 2^22
+ * vertices are decomposed by one persistent kernel, one workgroup per graph
+ * (largest first); larger graphs take the device-wide path after it.  Each
+ * graph is validated as an edge list; the failing graph of smallest index
+ * decides the returned code (the other graphs' outputs are then unspecified).
+ * The workspace holds the offsets, a scratch slot per concurrent workgroup
+ * (about 8 bytes per vertex and 48 per edge of the largest batched graph, for
+ * up to four workgroups per compute unit) and the device-wide path's workspace
+ * for the largest remaining graph. */
 int truss_batch_workspace_size(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
                                const truss_options *opts, size_t *bytes);
 int truss_batch(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
                 const int32_t *src, const int32_t *dst, int32_t *truss_out,
                 const truss_options *opts, truss_stats *stats, void *ws, size_t ws_bytes,
                 void *stream);
+
+/* A reusable batch: the offsets are copied to the workspace once and the
+ * device work (counter reset and the persistent kernel) is captured in a HIP
+ * graph, replayed by each truss_batch_plan_run.  The plan refers to src, dst,
+ * truss_out and ws, which must stay valid (and unchanged in shape) until
+ * truss_batch_plan_destroy.  The caller owns the plan (host memory). */
+typedef struct truss_batch_plan truss_batch_plan;
+int truss_batch_plan_create(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
+                            const int32_t *src, const int32_t *dst, int32_t *truss_out,
+                            const truss_options *opts, void *ws, size_t ws_bytes, void *stream,
+                            truss_batch_plan **plan);
+int truss_batch_plan_run(truss_batch_plan *plan, truss_stats *stats, void *stream);
+void truss_batch_plan_destroy(truss_batch_plan *plan);
+
+/* Times every built batch shape (threads per workgroup x lanes per edge) on a
+ * size-stratified sample of at most 512 of the batch's graphs and returns the
+ * fastest in *best_block, *best_lanes (host) and its time in *best_ms (host,
+ * nullable).  Writes the sampled graphs' truss numbers to truss_out. */
+int truss_batch_autotune(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
+                         const int32_t *src, const int32_t *dst, int32_t *truss_out,
+                         const truss_options *opts, void *ws, size_t ws_bytes, void *stream,
+                         int32_t *best_block, int32_t *best_lanes, float *best_ms);
 
 /* ---- tracing: the per-decision record behind the learned scheduler ----- */
 /* Peeling level actions: bit 0 = probe (0 hash table, 1 binary search),

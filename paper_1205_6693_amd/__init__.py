@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
                 ("peel_mode", ctypes.c_int32), ("scheduler", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("max_subrounds", ctypes.c_int64),
                 ("grid_blocks", ctypes.c_int32), ("peel_probe", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("batch_block", ctypes.c_int32), ("batch_lanes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -105,6 +106,13 @@ def load_library():
     lib.truss_decompose.argtypes = [gp, vp, op, sp, vp, ctypes.c_size_t, vp]
     lib.truss_batch_workspace_size.argtypes = [i32, vp, vp, op, ctypes.POINTER(ctypes.c_size_t)]
     lib.truss_batch.argtypes = [i32, vp, vp, vp, vp, vp, op, sp, vp, ctypes.c_size_t, vp]
+    lib.truss_batch_plan_create.argtypes = [i32, vp, vp, vp, vp, vp, op, vp, ctypes.c_size_t, vp,
+                                            ctypes.POINTER(ctypes.c_void_p)]
+    lib.truss_batch_plan_run.argtypes = [vp, sp, vp]
+    lib.truss_batch_plan_destroy.argtypes = [vp]
+    lib.truss_batch_plan_destroy.restype = None
+    lib.truss_batch_autotune.argtypes = [i32, vp, vp, vp, vp, vp, op, vp, ctypes.c_size_t, vp,
+                                         ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
     tp = ctypes.POINTER(Trace)
     f32, u64, fp = ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)
     szp = ctypes.POINTER(ctypes.c_size_t)
@@ -121,6 +129,7 @@ def load_library():
     lib.truss_sched_train.argtypes = [i32, vp, vp, i32, i32, i32, f32, u64, vp, fp, vp, ctypes.c_size_t, vp]
     for f in ("truss_workspace_size", "truss_support", "truss_decompose",
               "truss_batch_workspace_size", "truss_batch", "truss_version", "truss_decompose_traced",
+              "truss_batch_plan_create", "truss_batch_plan_run", "truss_batch_autotune",
               "truss_mlp_param_count", "truss_mlp_workspace_size", "truss_mlp_forward",
               "truss_mlp_backward", "truss_mlp_train", "truss_sched_part_floats",
               "truss_sched_model_floats", "truss_sched_train_workspace_size", "truss_sched_train"):
@@ -195,11 +204,13 @@ class Graph:
 
 
 def make_options(support_strategy=SUP_AUTO, peel_mode=PEEL_AUTO, scheduler=SCHED_HEURISTIC,
-                 model=None, max_subrounds=0, grid_blocks=0, peel_probe=PROBE_AUTO):
+                 model=None, max_subrounds=0, grid_blocks=0, peel_probe=PROBE_AUTO, batch_block=0,
+                 batch_lanes=0):
     o = Options()
     load_library().truss_default_options(ctypes.byref(o))
     o.support_strategy, o.peel_mode, o.scheduler = support_strategy, peel_mode, scheduler
     o.peel_probe = peel_probe
+    o.batch_block, o.batch_lanes = batch_block, batch_lanes
     o.model = _ptr(model).value if model is not None else None
     o.max_subrounds, o.grid_blocks = max_subrounds, grid_blocks
     return o
@@ -259,17 +270,23 @@ def truss_batch_workspace_size(vtx_off, edge_off, opts: Options | None = None) -
     return b.value
 
 
-def truss_batch(vtx_off, edge_off, src, dst, opts: Options | None = None, out=None, ws=None, stream=None):
-    """Truss numbers of many independent graphs packed together (graph-local ids)."""
+def _batch_args(vtx_off, edge_off, src, dst, out):
     import numpy as np
     torch = _torch()
-    lib = load_library()
     vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
     eo = np.ascontiguousarray(edge_off, dtype=np.int64)
     src = src.to(torch.int32).contiguous()
     dst = dst.to(torch.int32).contiguous()
     if out is None:
         out = torch.empty(src.numel(), dtype=torch.int32, device=src.device)
+    return vo, eo, src, dst, out
+
+
+def truss_batch(vtx_off, edge_off, src, dst, opts: Options | None = None, out=None, ws=None, stream=None):
+    """Truss numbers of many independent graphs packed together (graph-local ids)."""
+    torch = _torch()
+    lib = load_library()
+    vo, eo, src, dst, out = _batch_args(vtx_off, edge_off, src, dst, out)
     if ws is None:
         ws = torch.empty(max(1, truss_batch_workspace_size(vo, eo, opts)), dtype=torch.uint8,
                          device=src.device)
@@ -278,6 +295,58 @@ def truss_batch(vtx_off, edge_off, src, dst, opts: Options | None = None, out=No
                            ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
                            _stream(stream)))
     return out, st.to_dict()
+
+
+class BatchPlan:
+    """A reusable batch (truss_batch_plan_*): offsets uploaded once, device work
+    captured in a HIP graph and replayed by run()."""
+
+    def __init__(self, vtx_off, edge_off, src, dst, opts: Options | None = None, out=None, ws=None,
+                 stream=None):
+        torch = _torch()
+        lib = load_library()
+        self.vo, self.eo, self.src, self.dst, self.out = _batch_args(vtx_off, edge_off, src, dst, out)
+        self.opts = opts
+        self.ws = ws if ws is not None else torch.empty(
+            max(1, truss_batch_workspace_size(self.vo, self.eo, opts)), dtype=torch.uint8, device=self.src.device)
+        h = ctypes.c_void_p(0)
+        _check(lib.truss_batch_plan_create(len(self.vo) - 1, self.vo.ctypes.data, self.eo.ctypes.data,
+                                           _ptr(self.src), _ptr(self.dst), _ptr(self.out),
+                                           ctypes.byref(opts) if opts else None, _ptr(self.ws), self.ws.numel(),
+                                           _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        st = Stats()
+        _check(load_library().truss_batch_plan_run(self._h, ctypes.byref(st), _stream(stream)))
+        return self.out, st.to_dict()
+
+    def close(self):
+        if self._h and self._h.value:
+            load_library().truss_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def truss_batch_autotune(vtx_off, edge_off, src, dst, opts: Options | None = None, out=None, ws=None,
+                         stream=None):
+    """Fastest (threads per workgroup, lanes per edge) on a sample of the batch,
+    and its sample time in ms."""
+    torch = _torch()
+    lib = load_library()
+    vo, eo, src, dst, out = _batch_args(vtx_off, edge_off, src, dst, out)
+    if ws is None:
+        ws = torch.empty(max(1, truss_batch_workspace_size(vo, eo, opts)), dtype=torch.uint8, device=src.device)
+    tb, tl, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
+    _check(lib.truss_batch_autotune(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
+                                    ctypes.byref(opts) if opts else None, _ptr(ws), ws.numel(), _stream(stream),
+                                    ctypes.byref(tb), ctypes.byref(tl), ctypes.byref(ms)))
+    return tb.value, tl.value, ms.value
 
 
 def truss_decompose_traced(graph: Graph, opts: Options | None = None, level_cap: int = 4096, out=None,

@@ -63,18 +63,25 @@ int check_graph(const truss_graph* g) {
   return TRUSS_OK;
 }
 
-int check_opts(const truss_options* o) {
+}  // namespace
+
+int validate_options(const truss_options* o) {
   if (!o) return TRUSS_OK;
   if (o->version != TRUSS_VERSION) { set_last_error("options version mismatch"); return TRUSS_E_INVAL; }
   if (o->support_strategy < TRUSS_SUP_AUTO || o->support_strategy > TRUSS_SUP_MERGE ||
       o->peel_mode < TRUSS_PEEL_AUTO || o->peel_mode > TRUSS_PEEL_DENSE ||
       o->scheduler < TRUSS_SCHED_PLAIN || o->scheduler > TRUSS_SCHED_LEARNED ||
-      o->peel_probe < TRUSS_PROBE_AUTO || o->peel_probe > TRUSS_PROBE_BSEARCH) {
+      o->peel_probe < TRUSS_PROBE_AUTO || o->peel_probe > TRUSS_PROBE_BSEARCH ||
+      !(o->batch_block == 0 || o->batch_block == 256 || o->batch_block == 512 || o->batch_block == 1024) ||
+      !(o->batch_lanes == 0 || o->batch_lanes == 1 || o->batch_lanes == 4 || o->batch_lanes == 16 ||
+        o->batch_lanes == 64)) {
     set_last_error("option out of range");
     return TRUSS_E_INVAL;
   }
   return TRUSS_OK;
 }
+
+namespace {
 
 // Checks a learned model's two part headers (device memory) against the
 // network shapes the scheduler evaluates; fills the part pointers.
@@ -183,7 +190,7 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
                truss_trace* trace) {
   int rc = check_graph(g);
   if (rc) return rc;
-  rc = check_opts(opts_in);
+  rc = validate_options(opts_in);
   if (rc) return rc;
   if (g->m > 0 && !out) { set_last_error("output is NULL"); return TRUSS_E_INVAL; }
   if (trace && trace->level_cap < 0) { set_last_error("negative trace capacity"); return TRUSS_E_INVAL; }
@@ -305,7 +312,7 @@ void truss_default_options(truss_options* o) {
 int truss_workspace_size(const truss_graph* g, const truss_options* opts, size_t* bytes) {
   int rc = check_graph(g);
   if (rc) return rc;
-  rc = check_opts(opts);
+  rc = validate_options(opts);
   if (rc) return rc;
   if (!bytes) { set_last_error("bytes is NULL"); return TRUSS_E_INVAL; }
   Arena a;
@@ -334,74 +341,6 @@ int truss_decompose_traced(const truss_graph* g, int32_t* truss_out, const truss
   if (!trace) { set_last_error("trace is NULL"); return TRUSS_E_INVAL; }
   if (g && g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
   return run_single(g, true, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, trace);
-}
-
-int truss_batch_workspace_size(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off,
-                               const truss_options* opts, size_t* bytes) {
-  if (num_graphs < 0 || !bytes || (num_graphs > 0 && (!vtx_off || !edge_off))) {
-    set_last_error("bad batch arguments");
-    return TRUSS_E_INVAL;
-  }
-  size_t best = 0;
-  for (int32_t i = 0; i < num_graphs; ++i) {
-    truss_graph g;
-    memset(&g, 0, sizeof(g));
-    g.fmt = TRUSS_FMT_EDGES;
-    g.n = (int32_t)(vtx_off[i + 1] - vtx_off[i]);
-    g.m = edge_off[i + 1] - edge_off[i];
-    g.src = g.dst = reinterpret_cast<const int32_t*>(1);
-    size_t b = 0;
-    int rc = truss_workspace_size(&g, opts, &b);
-    if (rc) return rc;
-    if (b > best) best = b;
-  }
-  *bytes = best;
-  return TRUSS_OK;
-}
-
-int truss_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off, const int32_t* src,
-                const int32_t* dst, int32_t* truss_out, const truss_options* opts, truss_stats* stats, void* ws,
-                size_t ws_bytes, void* stream) {
-  if (num_graphs < 0 || (num_graphs > 0 && (!vtx_off || !edge_off))) {
-    set_last_error("bad batch arguments");
-    return TRUSS_E_INVAL;
-  }
-  if (stats) memset(stats, 0, sizeof(*stats));
-  for (int32_t i = 0; i < num_graphs; ++i) {
-    if (vtx_off[i + 1] < vtx_off[i] || edge_off[i + 1] < edge_off[i] || vtx_off[i + 1] - vtx_off[i] > 0x7fffffffLL) {
-      set_last_error("batch offsets of graph %d are not monotone", i);
-      return TRUSS_E_INVAL;
-    }
-    truss_graph g;
-    memset(&g, 0, sizeof(g));
-    g.fmt = TRUSS_FMT_EDGES;
-    g.n = (int32_t)(vtx_off[i + 1] - vtx_off[i]);
-    g.m = edge_off[i + 1] - edge_off[i];
-    g.src = src + edge_off[i];
-    g.dst = dst + edge_off[i];
-    truss_stats st;
-    int rc = truss_decompose(&g, truss_out + edge_off[i], opts, stats ? &st : nullptr, ws, ws_bytes, stream);
-    if (rc) return rc;
-    if (stats) {
-      stats->n += st.n;
-      stats->m += st.m;
-      if (st.kmax > stats->kmax) stats->kmax = st.kmax;
-      stats->levels += st.levels;
-      stats->subrounds += st.subrounds;
-      stats->peel_work += st.peel_work;
-      stats->ms_build += st.ms_build;
-      stats->ms_support += st.ms_support;
-      stats->ms_peel += st.ms_peel;
-      stats->ms_total += st.ms_total;
-      stats->triangles += st.triangles;
-      stats->launches += st.launches;
-      stats->heavy_rounds += st.heavy_rounds;
-      for (int b = 0; b < 6; ++b) stats->frontier_hist[b] += st.frontier_hist[b];
-      for (int b = 0; b < 6; ++b) stats->ms_phase[b] += st.ms_phase[b];
-      stats->ms_peel_kernel += st.ms_peel_kernel;
-    }
-  }
-  return TRUSS_OK;
 }
 
 const char* truss_strerror(int code) {

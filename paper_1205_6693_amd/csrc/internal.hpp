@@ -109,6 +109,7 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
          PeelResult* res, hipStream_t s, truss_trace* trace);
 
 void set_last_error(const char* fmt, ...);
+int validate_options(const truss_options* o);  // TRUSS_OK or TRUSS_E_INVAL (message set)
 int device_grid_blocks(const void* kernel, int block, size_t lds);
 
 }  // namespace truss

@@ -9,6 +9,7 @@ arrays, the triangle count, k_max and the size of every k-class.
 Usage: python tests/golden/make_golden.py rmat20      (about 5 minutes, one core)
        python tests/golden/make_golden.py chunglu4m   (the 57M-edge Chung-Lu graph; about 8 minutes)
        python tests/golden/make_golden.py rmat24      (260M edges; hours, about 30 GB of RAM)
+       python tests/golden/make_golden.py batch4096   (the 4096-graph batch; five processes)
 """
 import hashlib
 import os
@@ -37,6 +38,43 @@ def digest(a):
     return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
 
 
+def _batch_one(spec):
+    n, s, d = graphgen.batch_graph(spec)
+    phi, kmax = oracle.truss(n, s, d)
+    return phi, kmax, s.size
+
+
+def batch_main(workers=5):
+    """The 4096-graph batch: truss numbers of every graph, concatenated in
+    batch order, as one digest; per-graph k_max and edge counts alongside."""
+    from multiprocessing import Pool
+    specs = graphgen.batch_specs(4096, 1)
+    t0 = time.time()
+    with Pool(workers) as pool:
+        res = pool.map(_batch_one, specs, chunksize=16)
+    phi = np.concatenate([r[0] for r in res])
+    kmax = [int(r[1]) for r in res]
+    ms = [int(r[2]) for r in res]
+    h = hashlib.sha256(np.ascontiguousarray(phi, dtype=np.int32).tobytes()).hexdigest()
+    hist = np.bincount(phi)
+    lines = [
+        "# Oracle results for the batch of 4096 graphs (seed 1), edges in batch order.",
+        "# Written by tests/golden/make_golden.py batch4096 from oracle.truss, one call per graph",
+        "# (%.0f s on %d cores)." % (time.time() - t0, workers),
+        "graphs: 4096",
+        "m: %d" % phi.size,
+        "kmax: %d" % max(kmax),
+        "truss_sha256: %s" % h,
+        "class_sizes: %s" % " ".join("%d:%d" % (k, c) for k, c in enumerate(hist) if c),
+        "graph_kmax: %s" % " ".join(map(str, kmax)),
+        "graph_m: %s" % " ".join(map(str, ms)),
+    ]
+    path = os.path.join(HERE, "oracle_batch4096.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines[:8]))
+
+
 def main(name):
     n, s, d = WORKLOADS[name]()
     t0 = time.time()
@@ -62,4 +100,8 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "rmat20")
+    which = sys.argv[1] if len(sys.argv) > 1 else "rmat20"
+    if which == "batch4096":
+        batch_main()
+    else:
+        main(which)

@@ -61,8 +61,10 @@ def oracle_record(name):
                 continue
             key, val = line.split(":", 1)
             val = val.strip()
-            if key in ("n", "m", "triangles", "kmax"):
+            if key in ("n", "m", "triangles", "kmax", "graphs"):
                 rec[key] = int(val)
+            elif key in ("graph_kmax", "graph_m"):
+                rec[key] = [int(t) for t in val.split()]
             elif key == "class_sizes":
                 rec[key] = {int(a): int(b) for a, b in (t.split(":") for t in val.split())}
             else:

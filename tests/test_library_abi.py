@@ -45,7 +45,8 @@ def test_version_and_strerror(T):
 
 
 def test_struct_layouts_match_header(T):
-    # sizes of the ABI structs: graph 48 B, options 64 B, stats 200 B
+    # sizes of the ABI structs: graph 48 B, options 64 B, stats 200 B (options
+    # keep their size: batch_block and batch_lanes took two reserved words)
     assert ctypes.sizeof(T._Graph) == 48
     assert ctypes.sizeof(T.Options) == 64
     assert ctypes.sizeof(T.Stats) == 200
@@ -93,15 +94,28 @@ def test_argument_errors_before_device_work(T):
     assert b"workspace" in lib.truss_last_error()
 
 
-def test_batch_workspace_is_max_over_graphs(T):
+def test_batch_workspace_covers_slots_and_big_graphs(T):
     import numpy as np
+    lib = T.load_library()
+    # three small graphs: one scratch slot each, sized for the largest (180 edges)
     vo = np.array([0, 10, 30, 31], np.int64)
     eo = np.array([0, 20, 200, 200], np.int64)
-    sz = T.truss_batch_workspace_size(vo, eo)
-    lib = T.load_library()
+    small = T.truss_batch_workspace_size(vo, eo)
+    assert small >= 3 * 48 * 180
+    # one more graph above the persistent kernel's limit (2^21 edges) adds the
+    # device-wide path's workspace for it
+    big_m = (1 << 21) + 5
+    vo2 = np.append(vo, vo[-1] + 1_000_000)
+    eo2 = np.append(eo, eo[-1] + big_m)
+    with_big = T.truss_batch_workspace_size(vo2, eo2)
     b = ctypes.c_size_t(0)
-    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 20, 180)), None, ctypes.byref(b)) == 0
-    assert sz == b.value
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 1_000_000, big_m)), None, ctypes.byref(b)) == 0
+    assert with_big >= small + b.value
+    # bad offsets and bad batch shapes are rejected on the host
+    with pytest.raises(T.TrussError):
+        T.truss_batch_workspace_size(np.array([0, 5, 3], np.int64), np.array([0, 1, 2], np.int64))
+    with pytest.raises(T.TrussError):
+        T.truss_batch_workspace_size(vo, eo, T.make_options(batch_block=300))
 
 
 def test_trace_layout_and_network_sizes(T):
