@@ -33,6 +33,8 @@ WORKLOADS = {
     "er2000": "Erdos-Renyi G(n=2000, p=0.01), int32 edge list",
     "chunglu4m": "Chung-Lu n=4M, exponent 2.1, mean degree 30, cap 200k, 64 planted cliques U{50..500}, int32 CSR",
     "rmat24": "R-MAT scale 24, edge factor 16, same (a,b,c,d), int32 ids / int64 offsets CSR",
+    "batch4096": "4096 graphs, n ~ U{64..8192}, mean degree ~ U[4,64], even ER / odd R-MAT (.57,.19,.19,.05), "
+                 "packed int32 edge lists with int64 offsets",
 }
 
 
@@ -145,6 +147,106 @@ def cpu_baseline(sample_scale: int, seed: int):
                       % (sample_scale, s.size, t)}
 
 
+def bench_batch(args):
+    """The batch workload: one persistent batch kernel in a replayed HIP graph
+    (shape from the autotuner) against one truss_decompose call per graph."""
+    import torch
+    import graphgen
+    import paper_1205_6693_amd as T
+    T.load_library()
+    torch.cuda.set_device(0)
+    print("generating batch4096 seed %d" % args.seed, file=sys.stderr, flush=True)
+    gs = graphgen.batch(4096, args.seed)
+    vo, eo, s, d = graphgen.pack(gs)
+    m = int(eo[-1])
+    S, D = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
+    del gs
+    t = time.perf_counter()
+    blk, lanes, tune_ms = T.truss_batch_autotune(vo, eo, S, D)
+    print("autotune: %d threads x %d lanes (%.1f ms on the batch; tuning took %.1f s)"
+          % (blk, lanes, tune_ms, time.perf_counter() - t), file=sys.stderr, flush=True)
+    plan = T.BatchPlan(vo, eo, S, D, T.make_options(batch_block=blk, batch_lanes=lanes))
+    for i in range(args.warmup):
+        _, st = plan.run()
+        print("warmup %d: %.2f ms" % (i, st["ms_total"]), file=sys.stderr, flush=True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, st = plan.run()
+        stats.append(st)
+        print("step %d: %.2f ms" % (i, st["ms_total"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    st = stats[-1]
+    kms = float(np.mean([x["ms_peel_kernel"] for x in stats]))
+    # algorithmic bytes of the batch kernel, per unit (documented in DESIGN.md):
+    # 56 B per edge (input, canonical pair, CSR build and sort, output),
+    # 8 B per support walk entry, 16 B per peeling walk entry
+    alg = 56 * m + 8 * st["support_work"] + 16 * st["peel_work"]
+    achieved = alg / (kms * 1e-3) / 1e9
+    per_graph = None
+    if not args.no_compare:
+        o = T.make_options()
+        out = torch.empty(m, dtype=torch.int32, device="cuda:0")
+        graphs = [T.Graph.from_edges(int(vo[g + 1] - vo[g]), S[eo[g]:eo[g + 1]], D[eo[g]:eo[g + 1]])
+                  for g in range(4096)]
+        ws = torch.empty(max(T.truss_workspace_size(g, o) for g in graphs), dtype=torch.uint8, device="cuda:0")
+        for g in range(8):
+            T.truss_decompose(graphs[g], o, out=out[eo[g]:eo[g + 1]], ws=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for g in range(4096):
+            T.truss_decompose(graphs[g], o, out=out[eo[g]:eo[g + 1]], ws=ws)
+            if g % 512 == 511:
+                print("per-graph launches: %d graphs done" % (g + 1), file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        pg = time.perf_counter() - t1
+        per_graph = {"edges_per_s": m / pg, "ms_per_batch": pg * 1e3, "calls": 4096}
+        same = bool(torch.equal(out, plan.out))
+        per_graph["same_output"] = same
+    result = {
+        "metric": "truss-decomposed edges/s + HBM GB/s, plain vs learned-scheduled, 1 MI355X",
+        "value": m / (ms_per_step * 1e-3), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batch4096", "description": WORKLOADS["batch4096"], "seed": args.seed,
+                   "graphs": 4096, "m": m, "batch_block": blk, "batch_lanes": lanes},
+        "kmax": st["kmax"], "levels": st["levels"], "subrounds": st["subrounds"], "triangles": st["triangles"],
+        "support_work": st["support_work"], "peel_work": st["peel_work"], "batch_kernel_ms": kms,
+        "autotune_ms": tune_ms,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": measured_traffic("batch4096", "k_batch", 1), "kernel": "k_batch",
+                     "launches_per_step": 1, "avg_launch_ms": round(kms, 4), "bytes_per_launch": int(alg)},
+        "per_graph_launches": per_graph,
+    }
+    if per_graph:
+        result["batched_over_per_graph"] = result["value"] / per_graph["edges_per_s"]
+    if not args.no_cpu_baseline:
+        print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline_batch(args.seed)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline_batch(seed: int):
+    """The oracle on the first 256 graphs of the batch spec list (serial)."""
+    import graphgen
+    import oracle
+    oracle.build()
+    specs = graphgen.batch_specs(4096, seed)[:256]
+    tot, m = 0.0, 0
+    for sp in specs:
+        n, s, d = graphgen.batch_graph(sp)
+        t0 = time.perf_counter()
+        oracle.truss(n, s, d)
+        tot += time.perf_counter() - t0
+        m += s.size
+    return {"value": m / tot, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "serial C oracle, one thread, on the first 256 graphs of the batch (m=%d) in %.1f s"
+                      % (m, tot)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +275,9 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch4096":
+        bench_batch(args)
+        return
     import torch
     import paper_1205_6693_amd as T
     T.load_library()

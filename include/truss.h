@@ -137,7 +137,9 @@ typedef struct truss_stats {
   int64_t heavy_rounds;     /* sub-rounds in which long walks were cut into pieces */
   double ms_phase[6];       /* peeling time by phase: live-list sweep, level start,
                                frontier rounds, unused, dense re-scan, unused     */
-  double ms_peel_kernel;    /* time inside the persistent peeling kernel, all launches */
+  double ms_peel_kernel;    /* time inside the persistent peeling kernel, all launches
+                               (truss_batch: the batch kernel's graph launch)     */
+  int64_t support_work;     /* truss_batch: row entries walked while counting support */
 } truss_stats;
 
 /* Fills *opts with defaults: AUTO strategies, heuristic scheduler. */
@@ -198,10 +200,11 @@ int truss_batch_plan_create(int32_t num_graphs, const int64_t *vtx_off, const in
 int truss_batch_plan_run(truss_batch_plan *plan, truss_stats *stats, void *stream);
 void truss_batch_plan_destroy(truss_batch_plan *plan);
 
-/* Times every built batch shape (threads per workgroup x lanes per edge) on a
- * size-stratified sample of at most 512 of the batch's graphs and returns the
- * fastest in *best_block, *best_lanes (host) and its time in *best_ms (host,
- * nullable).  Writes the sampled graphs' truss numbers to truss_out. */
+/* Autotuner of the batch shape (threads per workgroup x lanes per edge): every
+ * built shape is timed on a size-stratified sample of at most 512 of the
+ * batch's graphs, then the three fastest on the whole batch; the fastest of
+ * those is returned in *best_block, *best_lanes (host) with its whole-batch
+ * time in *best_ms (host, nullable).  Leaves valid truss numbers in truss_out. */
 int truss_batch_autotune(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
                          const int32_t *src, const int32_t *dst, int32_t *truss_out,
                          const truss_options *opts, void *ws, size_t ws_bytes, void *stream,
@@ -218,7 +221,9 @@ int truss_batch_autotune(int32_t num_graphs, const int64_t *vtx_off, const int64
                                 previous level) */
 #define TRUSS_SCHED_PEEL_A 4
 /* Support bin actions: 0 LDS hash, 1 binary search, 2 merge (hash is not
- * available to the last bin, whose out-neighbourhoods exceed the LDS). */
+ * available to the last bin, whose out-neighbourhoods exceed the LDS).  The
+ * learned scheduler departs from the heuristic's method for a bin only when
+ * the network predicts it at least 2^0.25 times faster. */
 #define TRUSS_SCHED_SUP_BINS 4 /* out-degree 2..64, 65..1024, 1025..4096, larger */
 #define TRUSS_SCHED_SUP_F 6  /* log2(1+vertices), log2(1+sum d), log2(1+sum d^2),
                                 log2(1+mean d), log2(1+m), log2(1+sum d^2 / sum d) */

@@ -62,7 +62,8 @@ class Stats(ctypes.Structure):
                 ("ms_peel", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("sched_fallback", ctypes.c_int32), ("launches", ctypes.c_int32),
                 ("frontier_hist", ctypes.c_int64 * 6), ("heavy_rounds", ctypes.c_int64),
-                ("ms_phase", ctypes.c_double * 6), ("ms_peel_kernel", ctypes.c_double)]
+                ("ms_phase", ctypes.c_double * 6), ("ms_peel_kernel", ctypes.c_double),
+                ("support_work", ctypes.c_int64)]
 
     def to_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

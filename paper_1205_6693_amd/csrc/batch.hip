@@ -41,6 +41,8 @@ struct BatchCtl {
   int kmax;
   int pad;
   unsigned long long levels, subrounds, triangles3;
+  unsigned long long sup_work, peel_work;  // row entries walked (support, peeling)
+  unsigned long long t_phase[3];            // workgroup time in CSR build, support, peeling (10 ns ticks)
 };
 
 struct BatchArgs {
@@ -183,6 +185,7 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
     if (tid == 0) A.gerr[g] = 0;
     return;
   }
+  const unsigned long long t0 = wall_clock64();
   // 1. degrees of the canonical edges; range and self-loop checks (Section 2: simple graphs)
   for (int x = tid; x <= n; x += T) S.cur[x] = 0;
   if (tid == 0) L.err = kNoErr;
@@ -256,9 +259,12 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
     }
     return;
   }
+  const unsigned long long t1 = wall_clock64();
+  // live row lengths for peeling (cur is free after the scatter)
+  for (int x = tid; x < n; x += T) S.cur[x] = ldw(&S.rp[x + 1]) - ldw(&S.rp[x]);
   // 4. support (Definition 1): each edge walks its shorter endpoint row and
   // looks every neighbour up in the other row
-  unsigned long long tri3 = 0;
+  unsigned long long tri3 = 0, wsup = 0, wpeel = 0;
   for (int i = grp; i < m; i += kGroups) {
     const int u = ldw(&S.eu[i]), v = ldw(&S.ev[i]);
     const int ru = ldw(&S.rp[u]), du = ldw(&S.rp[u + 1]) - ru;
@@ -277,12 +283,15 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
       S.sup[i] = cnt;
       S.stamp[i] = 0;
       tri3 += (unsigned long long)cnt;
+      wsup += (unsigned long long)la;
     }
   }
+  __syncthreads();
+  const unsigned long long t2 = wall_clock64();
   // 5. peeling, level by level (Algorithm 2, Steps 4-15, level-synchronous)
   int32_t* alist[2] = {S.colA, S.colA + A.max_m};
   int32_t* fq[2] = {S.eidA, S.eidA + A.max_m};
-  int acnt = m, acur = 0;
+  int acnt = m, acur = 0, csr_live = m;
   bool first = true;
   int k = 1, r = 0, levels = 0, subrounds = 0;
   __syncthreads();
@@ -316,6 +325,36 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
     acur ^= 1;
     first = false;
     if (acnt == 0) break;
+    if (2 * acnt < csr_live) {
+      // drop removed entries from the rows once the live edge count has halved
+      // (stable, so rows stay sorted; a wavefront per row)
+      csr_live = acnt;
+      for (int x = wv; x < n; x += kWavesT) {
+        const int base = ldw(&S.rp[x]);
+        const int len = ldw(&S.cur[x]);
+        int wpos = 0;
+        for (int c0 = 0; c0 < len; c0 += kWave) {
+          const int j = c0 + lane;
+          int c = 0, ed = 0;
+          bool keep = false;
+          if (j < len) {
+            c = ldw(&S.col[base + j]);
+            ed = ldw(&S.eid[base + j]);
+            keep = ldw(&S.stamp[ed]) == 0;
+          }
+          const uint64_t km = ballot(keep);
+          wave_sync();
+          if (keep) {
+            S.col[base + wpos + rank_below(km)] = c;
+            S.eid[base + wpos + rank_below(km)] = ed;
+          }
+          wpos += __popcll(km);
+          wave_sync();
+        }
+        if (lane == 0) S.cur[x] = wpos;
+      }
+      __syncthreads();
+    }
     k = L.minv + 2 > k + 1 ? L.minv + 2 : k + 1;
     const int l = k - 2;
     ++levels;
@@ -354,8 +393,8 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
         if (has) {
           e = ldw(&Q[f]);
           const int u = ldw(&S.eu[e]), v = ldw(&S.ev[e]);
-          const int ru = ldw(&S.rp[u]), du = ldw(&S.rp[u + 1]) - ru;
-          const int rv = ldw(&S.rp[v]), dv = ldw(&S.rp[v + 1]) - rv;
+          const int ru = ldw(&S.rp[u]), du = ldw(&S.cur[u]);
+          const int rv = ldw(&S.rp[v]), dv = ldw(&S.cur[v]);
           const bool ua = du < dv || (du == dv && u < v);
           b = ua ? v : u;
           ra = ua ? ru : rv;
@@ -364,6 +403,7 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
           lb = ua ? dv : du;
         }
         const int trips = has ? (la + G - 1) / G : 0;
+        if (has && lg == 0) wpeel += (unsigned long long)la;
         // every lane of the wavefront runs the same number of appends
         int wtrips = trips;
 #pragma unroll
@@ -420,8 +460,18 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
   }
   // per-graph totals
   tri3 = wave_sum(tri3);
-  if (lane == 0 && tri3) atomicAdd(&A.ctl->triangles3, tri3);
+  wsup = wave_sum(wsup);
+  wpeel = wave_sum(wpeel);
+  if (lane == 0) {
+    if (tri3) atomicAdd(&A.ctl->triangles3, tri3);
+    if (wsup) atomicAdd(&A.ctl->sup_work, wsup);
+    if (wpeel) atomicAdd(&A.ctl->peel_work, wpeel);
+  }
   if (tid == 0) {
+    const unsigned long long t3 = wall_clock64();
+    atomicAdd(&A.ctl->t_phase[0], t1 - t0);
+    atomicAdd(&A.ctl->t_phase[1], t2 - t1);
+    atomicAdd(&A.ctl->t_phase[2], t3 - t2);
     A.gerr[g] = 0;
     atomicMax(&A.ctl->kmax, k);
     atomicAdd(&A.ctl->levels, (unsigned long long)levels);
@@ -455,6 +505,9 @@ __global__ void k_batch_init(BatchCtl* c, int32_t* gerr, int G) {
     c->levels = 0;
     c->subrounds = 0;
     c->triangles3 = 0;
+    c->sup_work = 0;
+    c->peel_work = 0;
+    for (int q = 0; q < 3; ++q) c->t_phase[q] = 0;
   }
 }
 
@@ -609,7 +662,7 @@ void plan_free(truss_batch_plan* p) {
 }
 
 // Reads the kernel's status and runs the device-wide path on the big graphs.
-int plan_finish(truss_batch_plan* p, truss_stats* stats, hipStream_t s) {
+int plan_finish(truss_batch_plan* p, truss_stats* stats, hipStream_t s, hipEvent_t done) {
   if (stats) memset(stats, 0, sizeof(*stats));
   int first_bad = kIntMax, bad_code = 0;
   truss_stats acc;
@@ -635,7 +688,9 @@ int plan_finish(truss_batch_plan* p, truss_stats* stats, hipStream_t s) {
     acc.kmax = std::max(acc.kmax, st.kmax);
     acc.levels += st.levels;
     acc.subrounds += st.subrounds;
+    acc.peel_work += st.peel_work;
   }
+  if (done) (void)hipEventRecord(done, s);
   BatchCtl h;
   TRUSS_HIP(hipMemcpyAsync(&h, p->lay.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
   TRUSS_HIP(hipStreamSynchronize(s));
@@ -655,6 +710,10 @@ int plan_finish(truss_batch_plan* p, truss_stats* stats, hipStream_t s) {
     stats->levels = (int32_t)(h.levels + (unsigned long long)acc.levels);
     stats->subrounds = (int64_t)h.subrounds + acc.subrounds;
     stats->launches = 1 + (int32_t)p->split.big.size();
+    stats->support_work = (int64_t)h.sup_work;
+    // workgroup time per phase (CSR build, support, peeling), summed over graphs
+    for (int q = 0; q < 3; ++q) stats->ms_phase[q] = (double)h.t_phase[q] * 1e-5;
+    stats->peel_work = (int64_t)h.peel_work + acc.peel_work;
   }
   return TRUSS_OK;
 }
@@ -786,8 +845,22 @@ int truss_batch_plan_run(truss_batch_plan* plan, truss_stats* stats, void* strea
     return TRUSS_E_INVAL;
   }
   hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  bool timed = stats != nullptr;
+  for (auto& x : e)
+    if (timed && hipEventCreate(&x) != hipSuccess) timed = false;
+  if (timed) (void)hipEventRecord(e[0], s);
   if (plan->exec) TRUSS_HIP(hipGraphLaunch(plan->exec, s));
-  return plan_finish(plan, stats, s);
+  if (timed) (void)hipEventRecord(e[1], s);
+  int rc = plan_finish(plan, stats, s, timed ? e[2] : nullptr);
+  if (!rc && timed) {
+    float k = 0.f, t = 0.f;
+    if (hipEventElapsedTime(&k, e[0], e[1]) == hipSuccess) stats->ms_peel_kernel = k;
+    if (hipEventElapsedTime(&t, e[0], e[2]) == hipSuccess) stats->ms_total = t;
+  }
+  for (auto& x : e)
+    if (x) (void)hipEventDestroy(x);
+  return rc;
 }
 
 void truss_batch_plan_destroy(truss_batch_plan* plan) { plan_free(plan); }
@@ -827,32 +900,54 @@ int truss_batch_autotune(int32_t num_graphs, const int64_t* vtx_off, const int64
     plan_free(p);
     return TRUSS_OK;
   }
-  TRUSS_HIP(hipMemcpyAsync(p->lay.order, sample.data(), sizeof(int32_t) * sample.size(), hipMemcpyHostToDevice, s));
-  BatchArgs A = p->args;
-  A.G = (int)sample.size();
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TRUSS_HIP(hipEventCreate(&e0));
   TRUSS_HIP(hipEventCreate(&e1));
+  // time one shape on the first `count` queue entries (order already on the device)
+  auto time_shape = [&](int T, int Gl, int count, int reps, float* ms) -> int {
+    BatchArgs A = p->args;
+    A.G = count;
+    float t = 0.f;
+    for (int rep = 0; rep < reps; ++rep) {
+      hipLaunchKernelGGL(k_batch_init, dim3((unsigned)((num_graphs + 256) / 256)), dim3(256), 0, s, p->lay.ctl,
+                         p->lay.gerr, num_graphs);
+      (void)hipEventRecord(e0, s);
+      int r = launch_batch(A, T, Gl, (int)std::min<size_t>((size_t)count, (size_t)p->split.slots), s);
+      if (r) return r;
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        return TRUSS_E_DEVICE;
+    }
+    *ms = t;
+    return TRUSS_OK;
+  };
+  // stage 1: every shape on the sample (the first run of each warms the caches)
+  TRUSS_HIP(hipMemcpyAsync(p->lay.order, sample.data(), sizeof(int32_t) * sample.size(), hipMemcpyHostToDevice, s));
   const int Ts[3] = {256, 512, 1024}, Gs[4] = {1, 4, 16, 64};
-  float best = -1.f;
+  struct Cand { float ms; int T, G; };
+  std::vector<Cand> cands;
   for (int ti = 0; ti < 3 && !rc; ++ti)
     for (int gi = 0; gi < 4 && !rc; ++gi) {
       float t = 0.f;
-      for (int rep = 0; rep < 2 && !rc; ++rep) {  // the first run warms the caches
-        hipLaunchKernelGGL(k_batch_init, dim3((unsigned)((num_graphs + 256) / 256)), dim3(256), 0, s, p->lay.ctl,
-                           p->lay.gerr, num_graphs);
-        (void)hipEventRecord(e0, s);
-        rc = launch_batch(A, Ts[ti], Gs[gi], (int)std::min<size_t>(sample.size(), p->split.slots), s);
-        (void)hipEventRecord(e1, s);
-        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = TRUSS_E_DEVICE;
-        if (!rc && hipEventElapsedTime(&t, e0, e1) != hipSuccess) rc = TRUSS_E_DEVICE;
-      }
+      rc = time_shape(Ts[ti], Gs[gi], (int)sample.size(), 2, &t);
+      if (!rc) cands.push_back({t, Ts[ti], Gs[gi]});
+    }
+  // stage 2: the three fastest on the whole queue, where the largest graphs
+  // (which set the tail) count at their full weight
+  float best = -1.f;
+  if (!rc) {
+    std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+    TRUSS_HIP(hipMemcpyAsync(p->lay.order, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice, s));
+    for (size_t c = 0; c < cands.size() && c < 3 && !rc; ++c) {
+      float t = 0.f;
+      rc = time_shape(cands[c].T, cands[c].G, (int)q.size(), 1, &t);
       if (!rc && (best < 0.f || t < best)) {
         best = t;
-        *best_block = Ts[ti];
-        *best_lanes = Gs[gi];
+        *best_block = cands[c].T;
+        *best_lanes = cands[c].G;
       }
     }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (!rc) {

@@ -114,7 +114,10 @@ __global__ void __launch_bounds__(kBinT) k_sup_bin(const int64_t* __restrict__ o
 // One wavefront per bin picks the bin's method.  force >= 0: that method for
 // every bin (hash becomes binary search in the last bin); otherwise by
 // scheduler: plain = merge; heuristic = hash, binary search in the last bin;
-// learned = the allowed method with the smallest model score.
+// learned = the allowed method with the smallest model score if that score is
+// below the heuristic method's by more than kSupMargin (log2 ms), else the
+// heuristic method.
+constexpr float kSupMargin = 0.25f;
 __global__ void __launch_bounds__(kBins * kWave) k_sup_decide(SupCtl* ctl, int64_t m, int sched, int force,
                                                                const float* __restrict__ model) {
   const int b = threadIdx.x / kWave;
@@ -135,9 +138,13 @@ __global__ void __launch_bounds__(kBins * kWave) k_sup_decide(SupCtl* ctl, int64
   } else if (sched == TRUSS_SCHED_PLAIN) {
     act = kMerge;
   } else if (sched == TRUSS_SCHED_LEARNED && model != nullptr) {
+    // the network's choice replaces the heuristic's only when it predicts a
+    // clear gain (a bin decides a large share of the support time at once)
     float sc[kSupA];
     mlp_scores_wave(model, x, sc);
-    act = argmin_allowed(sc, kSupA, allowed);
+    const int best = argmin_allowed(sc, kSupA, allowed);
+    const int pref = b == kBins - 1 ? kBsearch : kHash;
+    act = sc[best] < sc[pref] - kSupMargin ? best : pref;
   } else {
     act = b == kBins - 1 ? kBsearch : kHash;
   }

@@ -1,8 +1,8 @@
 """Trains the learned scheduler's model file (sched_model.json beside this file).
 
 Training graphs are seeded synthetic graphs (seeds >= 1000) smaller than the
-benchmark workloads: R-MAT (scales 14-19, edge factors 8-128), Chung-Lu
-power-law graphs with planted cliques (up to 2^20 vertices, cliques up to 4600
+largest workloads: R-MAT (scales 14-22, edge factors 8-128), Chung-Lu
+power-law graphs with planted cliques (up to 2^21 vertices, cliques up to 4600
 vertices) and Erdos-Renyi graphs.  For each, exhaustive timing (sched.exhaustive) records the time of
 every action at every decision; both model parts are then fitted on the GPU by
 the library's own forward, backward and Adam kernels.  Held-out graphs
@@ -43,6 +43,9 @@ TRAIN = [
     ("cl", 1 << 16, 20, 4, 1100, 2000, 1015), ("cl", 1 << 17, 20, 1, 4300, 4600, 1016),
     ("rmat", 15, 128, 1009),
     ("er", 20000, 1e-3, 1020), ("er", 100000, 3e-4, 1021), ("er", 4000, 1e-2, 1022),
+    # larger graphs (still below the R-MAT 24 and Chung-Lu 4M workloads)
+    ("rmat", 20, 16, 1030), ("rmat", 21, 16, 1031), ("rmat", 22, 16, 1032), ("rmat", 21, 8, 1033),
+    ("cl", 1 << 21, 30, 64, 50, 500, 1034),
 ]
 HELDOUT = [("rmat", 17, 16, 2000), ("cl", 1 << 19, 30, 48, 50, 400, 2001), ("rmat", 19, 12, 2002)]
 
