@@ -54,6 +54,9 @@ constexpr int kWaves = kT / kWave;
 constexpr int kSeg = 4 * 1024;  // adjacency entries per segment of a chunk's walks
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kHistBins = 6;
+constexpr long long kCompactNum = 7, kCompactDen = 10;  // row compaction threshold
+constexpr int kStageA = 8192;  // LDS staging of live-list appends (entries)
+constexpr int kStageQ = 2048;  // LDS staging of frontier-queue appends
 
 enum Phase : int {
   PH_SWEEP = 0,    // compact the live-edge list, minimum live support
@@ -212,7 +215,6 @@ __device__ void control_step(PeelCtl* c, const PeelArgs& P) {
   const unsigned long long now = wall_clock64();
   int qlen_out = -1, mode_out = -1, probe_out = -1, first_out = -1, hist_bin_out = -1;
   bool reset_sweep = false, reset_queue = false, reset_proc = false;
-  const int li = levels - 1;  // trace row of the current level
 
   auto begin_round = [&](int q) {
     qlen_out = q;
@@ -228,11 +230,13 @@ __device__ void control_step(PeelCtl* c, const PeelArgs& P) {
       begin_round(w_qlen);
     } else {
       // level finished
+      const int li = levels - 1;
       if (lead && li < P.tr_cap && P.tr_ms) P.tr_ms[li] = (float)((double)(now - t_dec) * 1e-5);
       prev_sub = subrounds - lvl_sub0;
-      // compact the rows when the live count has halved
+      // compact the rows when the live count has dropped below kCompactNum /
+      // kCompactDen of the entries they hold
       const long long alive_after = (long long)acnt - removed_level;
-      if (alive_after > 0 && alive_after * 2 < csr_live) {
+      if (alive_after > 0 && alive_after * kCompactDen < csr_live * kCompactNum) {
         csr_live = alive_after;
         phase = PH_COMPACT;
       } else {
@@ -240,29 +244,9 @@ __device__ void control_step(PeelCtl* c, const PeelArgs& P) {
       }
     }
   };
-  switch (phase) {
-    case PH_SWEEP:
-      reset_sweep = true;
-      acnt = w_alive;
-      acur ^= 1;
-      first_out = 0;
-      if (w_alive == 0) {
-        phase = PH_DONE;
-        break;
-      }
-      k = (w_minsup + 2 > k + 1) ? w_minsup + 2 : k + 1;
-      levels += 1;
-      r += 1;
-      removed_level = 0;
-      reset_queue = true;
-      phase = PH_START;
-      break;
-    case PH_START:
-      reset_queue = true;
-      removed_level = w_qlen;
-      if (w_qlen > 0) {
-        // the level's decision, from features that are the same whatever
-        // earlier levels chose
+  // the level's decision, from features that are the same whatever earlier
+  // levels chose; then the level's first round
+  auto start_level = [&]() {
         float x[kPeelF];
         const float live = (float)acnt, f0 = (float)w_qlen, wk = (float)w_fwork;
         x[0] = log2f(1.f + live);
@@ -287,6 +271,7 @@ __device__ void control_step(PeelCtl* c, const PeelArgs& P) {
         }
         mode_out = (act & 2) ? (int)TRUSS_PEEL_DENSE : (int)TRUSS_PEEL_SPARSE;
         probe_out = act & 1;
+        const int li = levels - 1;  // trace row of the level
         if (lead && li < P.tr_cap && P.tr_feat) {
           for (int i = 0; i < kPeelF; ++i) P.tr_feat[(int64_t)li * kPeelF + i] = x[i];
           P.tr_act[li] = act;
@@ -294,9 +279,39 @@ __device__ void control_step(PeelCtl* c, const PeelArgs& P) {
         lvl_sub0 = subrounds;
         t_dec = now;
         begin_round(w_qlen);
-      } else {
-        phase = PH_SWEEP;
+  };
+  switch (phase) {
+    case PH_SWEEP:
+      // the sweep has also taken the live edges with sup <= k-1, the frontier
+      // of level k+1 (stamped r+1); it is the level's F_0 unless empty, which
+      // happens exactly when the minimum live support is at least k, so that
+      // the next level is min + 2 and needs its own start phase
+      reset_sweep = true;
+      reset_queue = true;
+      acnt = w_alive;
+      acur ^= 1;
+      first_out = 0;
+      if (w_alive == 0) {
+        phase = PH_DONE;
+        break;
       }
+      levels += 1;
+      r += 1;
+      if (w_qlen > 0) {
+        k = k + 1;
+        removed_level = w_qlen;
+        start_level();
+      } else {
+        k = w_minsup + 2;
+        removed_level = 0;
+        phase = PH_START;
+      }
+      break;
+    case PH_START:
+      reset_queue = true;
+      removed_level = w_qlen;
+      if (w_qlen > 0) start_level();
+      else phase = PH_SWEEP;
       break;
     case PH_PROC:
       reset_proc = true;
@@ -489,24 +504,76 @@ __device__ __forceinline__ void wq_push(WaveQueue& wq, int32_t f1, int32_t f2) {
   if (wq.cnt >= kWave) wq_flush(wq);
 }
 
-// Block-wide append: every thread with `want` gets a distinct slot of the
-// global counter; one atomic per workgroup.  tmp: kWaves + 1 ints of LDS.
-__device__ __forceinline__ int block_append(int* counter, bool want, int* tmp) {
+// Appends of a whole workgroup gathered in LDS and written to a global list in
+// bulk, so that the list's counter sees one atomic per flush rather than one
+// per 1024 entries.  Every thread of the workgroup calls append() and flush().
+struct StagedList {
+  int* buf;       // LDS, cap entries
+  int cap;
+  int* fill;      // LDS: entries held
+  int* base;      // LDS: list position of a flush
+  int* counter;   // global list length
+  int32_t* out;   // global list
+};
+
+__device__ __forceinline__ void staged_flush(StagedList& L) {
+  __syncthreads();
+  const int n = *L.fill;
+  if (n == 0) return;
+  if (threadIdx.x == 0) *L.base = atomicAdd(L.counter, n);
+  __syncthreads();
+  const int b = *L.base;
+  for (int i = threadIdx.x; i < n; i += kT) stc(&L.out[b + i], L.buf[i]);
+  __syncthreads();
+  if (threadIdx.x == 0) *L.fill = 0;
+  __syncthreads();
+}
+
+// tmp: kWaves ints of LDS
+__device__ __forceinline__ void staged_append(StagedList& L, bool want, int32_t val, int* tmp) {
   const int lane = lane_id(), w = threadIdx.x / kWave;
   const uint64_t m = ballot(want);
   if (lane == 0) tmp[w] = __popcll(m);
   __syncthreads();
+  int wbase = 0, tot = 0;
+  for (int q = 0; q < kWaves; ++q) {
+    const int x = tmp[q];
+    if (q < w) wbase += x;
+    tot += x;
+  }
+  if (*L.fill + tot > L.cap) staged_flush(L);
+  const int f = *L.fill;
+  if (want) L.buf[f + wbase + rank_below(m)] = val;
+  __syncthreads();
+  if (threadIdx.x == 0) *L.fill = f + tot;
+  __syncthreads();
+}
+
+// minimum over the workgroup into *dst (one atomic per workgroup); tmp: kWaves ints
+__device__ __forceinline__ void block_min_to(int x, int* tmp, int* dst) {
+  x = wave_min(x);
+  if (lane_id() == 0) tmp[threadIdx.x / kWave] = x;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    int run = 0;
-    for (int q = 0; q < kWaves; ++q) {
-      const int x = tmp[q];
-      tmp[q] = run;
-      run += x;
-    }
-    tmp[kWaves] = run ? atomicAdd(counter, run) : 0;
+    int v = kIntMax;
+    for (int q = 0; q < kWaves; ++q) v = tmp[q] < v ? tmp[q] : v;
+    if (v != kIntMax) atomicMin(dst, v);
   }
   __syncthreads();
-  return tmp[kWaves] + tmp[w] + rank_below(m);
+}
+
+// sum over the workgroup into *dst (one atomic per workgroup); tmp: kWaves entries
+__device__ __forceinline__ void block_sum_to(unsigned long long x, unsigned long long* tmp,
+                                             unsigned long long* dst) {
+  x = wave_sum(x);
+  if (lane_id() == 0) tmp[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long v = 0;
+    for (int q = 0; q < kWaves; ++q) v += tmp[q];
+    if (v) atomicAdd(dst, v);
+  }
+  __syncthreads();
 }
 
 // Block-wide inclusive prefix sum of one int per thread; total in *total.
@@ -536,7 +603,15 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
   __shared__ int s_c0;
   __shared__ unsigned long long s_pv;
   __shared__ unsigned long long s_w64[kWaves];
+  __shared__ int s_stage_a[kStageA];
+  __shared__ int s_stage_q[kStageQ];
+  __shared__ int s_fill[4];
   PeelCtl* c = P.ctl;
+  if (threadIdx.x == 0) {
+    s_fill[0] = 0;
+    s_fill[2] = 0;
+  }
+  __syncthreads();
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
@@ -550,33 +625,50 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
     const int r = ldc(&c->r);
     const int acur = ldc(&c->acur);
     if (phase == PH_SWEEP) {
-      // live-edge list of the new level; minimum live support
+      // live-edge list of the new level and its minimum support; the live
+      // edges with sup <= k-1 are taken at once as the frontier of level k+1
+      // (the control step keeps them only if that level is not skipped, in
+      // which case none is taken)
       const int first = ldc(&c->first);
       const int64_t cnt = first ? P.m : (int64_t)ldc(&c->acnt);
       const int32_t* A = P.alist[acur];
-      int32_t* B = P.alist[acur ^ 1];
+      StagedList LA{s_stage_a, kStageA, &s_fill[0], &s_fill[1], &c->w_alive, P.alist[acur ^ 1]};
+      StagedList LQ{s_stage_q, kStageQ, &s_fill[2], &s_fill[3], &c->w_qlen, P.fq[(r + 1) & 1]};
+      const int kt = k + 1, stamp = r + 1;
       int mins = kIntMax;
+      unsigned long long wsum = 0;
       for (int64_t base = (int64_t)blockIdx.x * kT; base < cnt; base += (int64_t)gridDim.x * kT) {
         const int64_t i = base + tid;
-        bool live = false;
+        bool live = false, take = false;
         int32_t e = 0;
         if (i < cnt) {
           e = first ? (int32_t)i : ldc(&A[i]);
           const int2 sv = ldc2(&P.sr[e]);
           live = sv.y == 0;
-          if (live && sv.x < mins) mins = sv.x;
+          if (live) {
+            mins = sv.x < mins ? sv.x : mins;
+            take = sv.x <= kt - 2;
+            if (take) {
+              stc_stamp(&P.sr[e], stamp);
+              P.truss[e] = kt;
+              const int du = P.rlen[P.eu[e]], dv = P.rlen[P.ev[e]];
+              wsum += (unsigned long long)(du < dv ? du : dv);
+            }
+          }
         }
-        const int pos = block_append(&c->w_alive, live, s_tmp);
-        if (live) stc(&B[pos], e);
+        staged_append(LA, live, e, s_tmp);
+        staged_append(LQ, take, e, s_tmp);
       }
-      mins = wave_min(mins);
-      if (lane == 0 && mins != kIntMax) atomicMin(&c->w_minsup, mins);
+      staged_flush(LA);
+      staged_flush(LQ);
+      block_min_to(mins, s_tmp, &c->w_minsup);
+      block_sum_to(wsum, s_w64, &c->w_fwork);
     } else if (phase == PH_START || phase == PH_DENSE) {
-      // collect live edges with sup <= k-2 (level start, or dense re-scan)
+      // collect live edges with sup <= k-2 (level start after a skip, or dense re-scan)
       const int64_t cnt = ldc(&c->acnt);
       const int32_t* A = P.alist[acur];
       const int stamp = phase == PH_START ? r : r + 1;
-      int32_t* Q = P.fq[stamp & 1];
+      StagedList LQ{s_stage_q, kStageQ, &s_fill[2], &s_fill[3], &c->w_qlen, P.fq[stamp & 1]};
       unsigned long long wsum = 0;  // level start: shorter live row over the frontier
       for (int64_t base = (int64_t)blockIdx.x * kT; base < cnt; base += (int64_t)gridDim.x * kT) {
         const int64_t i = base + tid;
@@ -595,19 +687,10 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
             }
           }
         }
-        const int pos = block_append(&c->w_qlen, take, s_tmp);
-        if (take) stc(&Q[pos], e);
+        staged_append(LQ, take, e, s_tmp);
       }
-      if (phase == PH_START) {
-        wsum = wave_sum(wsum);
-        if (lane == 0) s_w64[wv] = wsum;
-        __syncthreads();
-        if (tid == 0) {
-          unsigned long long t = 0;
-          for (int q = 0; q < kWaves; ++q) t += s_w64[q];
-          if (t) atomicAdd(&c->w_fwork, t);
-        }
-      }
+      staged_flush(LQ);
+      if (phase == PH_START) block_sum_to(wsum, s_w64, &c->w_fwork);
     } else if (phase == PH_PROC) {
       const int qn = ldc(&c->qlen);
       const bool sparse = ldc(&c->mode) == TRUSS_PEEL_SPARSE;
