@@ -51,7 +51,7 @@ namespace {
 
 constexpr int kT = 1024;
 constexpr int kWaves = kT / kWave;
-constexpr int kSeg = 4 * 1024;  // adjacency entries per segment of a chunk's walks
+constexpr int kSeg = 4 * 1024;  // adjacency entries per segment of a chunk's walks (kNI per thread)
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kHistBins = 6;
 constexpr long long kCompactNum = 7, kCompactDen = 10;  // row compaction threshold
@@ -427,47 +427,105 @@ __device__ bool phase_barrier(PeelCtl* c, const PeelArgs& P) {
 
 __device__ __forceinline__ bool removed_at(int rnd, int r) { return rnd != 0 && rnd < r; }
 
-// One adjacency entry j of the walk of frontier edge e = (a, b).  Outputs the
-// (up to two) edges whose support crossed k-1 -> k-2 and must be enqueued.
-__device__ __forceinline__ void process_entry(const PeelArgs& P, int32_t e, int32_t b, int64_t j, int r, int l, int k,
-                                              bool sparse, int probe, int32_t& f1, int32_t& f2) {
-  f1 = -1;
-  f2 = -1;
-  const int32_t w = P.col[j];
-  if (w == b) return;
-  const int32_t e1 = P.seid[j];
-  const int rnd1 = ldc_stamp(&P.sr[e1]);
-  if (removed_at(rnd1, r)) return;
-  int32_t e2;
-  if (probe == 0) {
-    e2 = edge_lookup(P.etab, P.etab_mask, b, w);
-    if (e2 < 0) return;
-  } else {
-    const int64_t rb = P.row_ptr[b];
-    const int64_t re = rb + P.rlen[b];
-    const int64_t p = lower_bound_i32<int64_t>(P.col, rb, re, w);
-    if (p >= re || P.col[p] != w) return;
-    e2 = P.seid[p];
-  }
-  const int rnd2 = ldc_stamp(&P.sr[e2]);
-  if (removed_at(rnd2, r)) return;
-  // the triangle belongs to its frontier edge of smallest id
-  if (rnd1 == r && e1 < e) return;
-  if (rnd2 == r && e2 < e) return;
-  if (rnd1 != r) {
-    const int old = atomicSub(&P.sr[e1].x, 1);
-    if (sparse && old == l + 1) {
-      stc_stamp(&P.sr[e1], r + 1);
-      P.truss[e1] = k;
-      f1 = e1;
+// kNI adjacency entries of walks, one step at a time for all of them so that
+// their memory accesses are in flight together.  Entry q is position j[q] of
+// the row walked for frontier edge e[q] = (a, b[q]), valid if ok[q].  Outputs
+// the (up to two) edges per entry whose support crossed k-1 -> k-2 and must be
+// enqueued.
+constexpr int kNI = 4;
+
+__device__ __forceinline__ ulonglong2 load_slot(const EdgeSlot* tab, unsigned long long h) {
+  return *reinterpret_cast<const ulonglong2*>(&tab[h]);
+}
+
+__device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t (&e)[kNI], const int32_t (&b)[kNI],
+                                                const int64_t (&j)[kNI], bool (&ok)[kNI], int r, int l, int k,
+                                                bool sparse, int probe, int32_t (&f1)[kNI], int32_t (&f2)[kNI]) {
+  int32_t w[kNI], e1[kNI], e2[kNI], s1[kNI], s2[kNI];
+#pragma unroll
+  for (int q = 0; q < kNI; ++q) {
+    f1[q] = -1;
+    f2[q] = -1;
+    w[q] = -1;
+    e1[q] = 0;
+    e2[q] = 0;
+    s1[q] = 0;
+    s2[q] = 0;
+    if (ok[q]) {
+      w[q] = P.col[j[q]];
+      e1[q] = P.seid[j[q]];
     }
   }
-  if (rnd2 != r) {
-    const int old = atomicSub(&P.sr[e2].x, 1);
-    if (sparse && old == l + 1) {
-      stc_stamp(&P.sr[e2], r + 1);
-      P.truss[e2] = k;
-      f2 = e2;
+  // the first other edge (a, w) must not be removed
+#pragma unroll
+  for (int q = 0; q < kNI; ++q) {
+    ok[q] = ok[q] && w[q] != b[q];
+    if (ok[q]) s1[q] = ldc_stamp(&P.sr[e1[q]]);
+  }
+#pragma unroll
+  for (int q = 0; q < kNI; ++q) ok[q] = ok[q] && !removed_at(s1[q], r);
+  // the second other edge (b, w), Step 8: hash table or binary search
+  if (probe == 0) {
+    unsigned long long key[kNI], h[kNI];
+    ulonglong2 sl[kNI];
+#pragma unroll
+    for (int q = 0; q < kNI; ++q) {
+      key[q] = edge_key(b[q], w[q]);
+      h[q] = mix64(key[q]) & P.etab_mask;
+      sl[q] = make_ulonglong2(kEmptyKey, 0ULL);
+      if (ok[q]) sl[q] = load_slot(P.etab, h[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kNI; ++q) {
+      if (!ok[q]) continue;
+      while (sl[q].x != key[q] && sl[q].x != kEmptyKey) {
+        h[q] = (h[q] + 1) & P.etab_mask;
+        sl[q] = load_slot(P.etab, h[q]);
+      }
+      if (sl[q].x == key[q]) e2[q] = (int32_t)(uint32_t)sl[q].y;
+      else ok[q] = false;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kNI; ++q) {
+      if (!ok[q]) continue;
+      const int64_t rb = P.row_ptr[b[q]];
+      const int64_t re = rb + P.rlen[b[q]];
+      const int64_t p = lower_bound_i32<int64_t>(P.col, rb, re, w[q]);
+      if (p < re && P.col[p] == w[q]) e2[q] = P.seid[p];
+      else ok[q] = false;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kNI; ++q)
+    if (ok[q]) s2[q] = ldc_stamp(&P.sr[e2[q]]);
+  // the triangle is destroyed now unless an edge is removed, and it belongs
+  // to its frontier edge of smallest id; each other edge not in F_r loses one
+  bool d1[kNI], d2[kNI];
+  int old1[kNI], old2[kNI];
+#pragma unroll
+  for (int q = 0; q < kNI; ++q) {
+    const bool live = ok[q] && !removed_at(s2[q], r) && !(s1[q] == r && e1[q] < e[q]) &&
+                      !(s2[q] == r && e2[q] < e[q]);
+    d1[q] = live && s1[q] != r;
+    d2[q] = live && s2[q] != r;
+    old1[q] = 0;
+    old2[q] = 0;
+    if (d1[q]) old1[q] = atomicSub(&P.sr[e1[q]].x, 1);
+    if (d2[q]) old2[q] = atomicSub(&P.sr[e2[q]].x, 1);
+  }
+  if (!sparse) return;
+#pragma unroll
+  for (int q = 0; q < kNI; ++q) {
+    if (d1[q] && old1[q] == l + 1) {
+      stc_stamp(&P.sr[e1[q]], r + 1);
+      P.truss[e1[q]] = k;
+      f1[q] = e1[q];
+    }
+    if (d2[q] && old2[q] == l + 1) {
+      stc_stamp(&P.sr[e2[q]], r + 1);
+      P.truss[e2[q]] = k;
+      f2[q] = e2[q];
     }
   }
 }
@@ -701,18 +759,31 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       unsigned long long* slots = P.pslot;
       // walk items [lo, hi) of the chunk held in the workgroup's LDS tables
       auto walk = [&](int lo, int hi) {
-        for (int t0 = lo; t0 < hi; t0 += kT) {
-          const int t = t0 + tid;
-          int32_t f1 = -1, f2 = -1;
-          if (t < hi) {
-            int x = 0, y = kT - 1;  // last edge whose range starts at or before t
-            while (x < y) {
-              const int mid = (x + y + 1) >> 1;
-              if (s_pre[mid] <= t) x = mid; else y = mid - 1;
+        for (int t0 = lo; t0 < hi; t0 += kNI * kT) {
+          int32_t e[kNI], b[kNI], f1[kNI], f2[kNI];
+          int64_t j[kNI];
+          bool ok[kNI];
+#pragma unroll
+          for (int q = 0; q < kNI; ++q) {
+            const int t = t0 + q * kT + tid;
+            ok[q] = t < hi;
+            e[q] = 0;
+            b[q] = 0;
+            j[q] = 0;
+            if (ok[q]) {
+              int x = 0, y = kT - 1;  // last edge whose range starts at or before t
+              while (x < y) {
+                const int mid = (x + y + 1) >> 1;
+                if (s_pre[mid] <= t) x = mid; else y = mid - 1;
+              }
+              e[q] = s_e[x];
+              b[q] = s_b[x];
+              j[q] = s_base[x] + (t - s_pre[x]);
             }
-            process_entry(P, s_e[x], s_b[x], s_base[x] + (t - s_pre[x]), r, l, k, sparse, probe, f1, f2);
           }
-          wq_push(wq, f1, f2);
+          process_entries(P, e, b, j, ok, r, l, k, sparse, probe, f1, f2);
+#pragma unroll
+          for (int q = 0; q < kNI; ++q) wq_push(wq, f1[q], f2[q]);
         }
         if (tid == 0) my_work += (unsigned long long)(hi - lo);
       };
