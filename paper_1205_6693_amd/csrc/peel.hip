@@ -57,6 +57,15 @@ constexpr int kHistBins = 6;
 constexpr long long kCompactNum = 7, kCompactDen = 10;  // row compaction threshold
 constexpr int kStageA = 8192;  // LDS staging of live-list appends (entries)
 constexpr int kStageQ = 2048;  // LDS staging of frontier-queue appends
+constexpr int kMinChunk = 64;  // smallest frontier chunk
+
+// Frontier edges per chunk in a round with qn frontier edges: the frontier is
+// spread over all workgroups, with between kMinChunk and kT edges a chunk.
+__device__ __forceinline__ int chunk_size(int qn, int groups) {
+  int cs = (qn + groups - 1) / groups;
+  cs = (cs + kMinChunk - 1) / kMinChunk * kMinChunk;
+  return cs < kMinChunk ? kMinChunk : cs > kT ? kT : cs;
+}
 
 enum Phase : int {
   PH_SWEEP = 0,    // compact the live-edge list, minimum live support
@@ -787,14 +796,17 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         }
         if (tid == 0) my_work += (unsigned long long)(hi - lo);
       };
-      // (1) frontier edges in chunks of kT, one edge a thread (the first chunk
-      // of every workgroup is static, the rest are fetched).  The walks of a
-      // chunk are laid end to end and cut into segments of kSeg entries; the
-      // workgroup walks segment 0 and announces the others for any workgroup
-      // to take.  A segment is announced by one 64-bit store into a slot.
+      // (1) frontier edges in chunks of cs <= kT, one edge a thread (the first
+      // chunk of every workgroup is static, the rest are fetched).  Small
+      // frontiers are spread over all workgroups (cs ~ |F| / workgroups, at
+      // least 64).  The walks of a chunk are laid end to end and cut into
+      // segments of kSeg entries; the workgroup walks segment 0 and announces
+      // the others for any workgroup to take.  A segment is announced by one
+      // 64-bit store into a slot.
+      const int cs = chunk_size(qn, (int)gridDim.x);
       bool first_chunk = true;
       for (;;) {
-        if (tid == 0) s_c0 = first_chunk ? (int)blockIdx.x * kT : (int)gridDim.x * kT + atomicAdd(&c->w_fetch, kT);
+        if (tid == 0) s_c0 = first_chunk ? (int)blockIdx.x * cs : (int)gridDim.x * cs + atomicAdd(&c->w_fetch, cs);
         first_chunk = false;
         __syncthreads();
         const int c0 = s_c0;
@@ -802,7 +814,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         const int i = c0 + tid;
         int32_t e = 0, a = 0, b = 0;
         int work = 0;
-        if (i < qn) {
+        if (tid < cs && i < qn) {
           e = ldc(&Q[i]);
           const int32_t u = P.eu[e], v = P.ev[e];
           const int du = P.rlen[u], dv = P.rlen[v];
@@ -823,11 +835,13 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         int npub = 0;  // segments 1..npub are announced
         if (nseg > 1) {
           // chunk tables for other workgroups, then the segment announcements
-          stc(&P.rec_e[i], e);
-          stc(&P.rec_b[i], b);
-          stc(&P.rec_base[i], ra);
-          stc(&P.rec_pre[i], inc - work);
-          if (tid == 0) stc(&P.rec_tot[c0 / kT], W);
+          if (tid < cs) {
+            stc(&P.rec_e[i], e);
+            stc(&P.rec_b[i], b);
+            stc(&P.rec_base[i], ra);
+            stc(&P.rec_pre[i], inc - work);
+          }
+          if (tid == 0) stc(&P.rec_tot[c0 / cs], W);
           mem_wait();
           __syncthreads();
           if (tid == 0) s_pv = atomicAdd(&c->w_pieces, (unsigned long long)(nseg - 1));
@@ -852,7 +866,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       // with fewer announcements than the index (then stops).  Indices are
       // drawn in order and never dropped, so each announced slot is taken
       // exactly once.
-      const int nchunks = (qn + kT - 1) / kT;
+      const int nchunks = (qn + cs - 1) / cs;
       for (;;) {
         if (tid == 0) {
           unsigned long long pv = ~0ULL;
@@ -913,12 +927,12 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         const int c0 = (int)(pv >> 32) - 1;
         const int sg = (int)(pv & 0xffffffffu);
         const int i = c0 + tid;
-        const bool ok = i < qn;
+        const bool ok = tid < cs && i < qn;
         s_pre[tid] = ok ? ldc(&P.rec_pre[i]) : kIntMax;
         s_e[tid] = ok ? ldc(&P.rec_e[i]) : 0;
         s_b[tid] = ok ? ldc(&P.rec_b[i]) : 0;
         s_base[tid] = ok ? ldc(&P.rec_base[i]) : 0;
-        const int W = ldc(&P.rec_tot[c0 / kT]);
+        const int W = ldc(&P.rec_tot[c0 / cs]);
         if (tid == 0) s_pre[kT] = W;
         __syncthreads();
         walk(sg * kSeg, (sg + 1) * kSeg < W ? (sg + 1) * kSeg : W);
@@ -1042,7 +1056,7 @@ void carve(const DevGraph& dg, Arena& a, PeelLayout& L) {
   L.rec_b = a.take<int32_t>(m + kT);
   L.rec_pre = a.take<int32_t>(m + kT);
   L.rec_base = a.take<int64_t>(m + kT);
-  L.rec_tot = a.take<int32_t>(m / kT + 2);
+  L.rec_tot = a.take<int32_t>(m / kMinChunk + 2);
 }
 
 int g_peel_blocks = 0;
