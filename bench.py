@@ -162,9 +162,13 @@ def bench_batch(args):
     S, D = torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda()
     del gs
     t = time.perf_counter()
-    blk, lanes, tune_ms = T.truss_batch_autotune(vo, eo, S, D)
-    print("autotune: %d threads x %d lanes (%.1f ms on the batch; tuning took %.1f s)"
-          % (blk, lanes, tune_ms, time.perf_counter() - t), file=sys.stderr, flush=True)
+    if args.batch_shape:
+        blk, lanes = args.batch_shape
+        tune_ms = None
+    else:
+        blk, lanes, tune_ms = T.truss_batch_autotune(vo, eo, S, D)
+        print("autotune: %d threads x %d lanes (%.1f ms on the batch; tuning took %.1f s)"
+              % (blk, lanes, tune_ms, time.perf_counter() - t), file=sys.stderr, flush=True)
     plan = T.BatchPlan(vo, eo, S, D, T.make_options(batch_block=blk, batch_lanes=lanes))
     for i in range(args.warmup):
         _, st = plan.run()
@@ -256,6 +260,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--scheduler", default="learned", choices=["plain", "heuristic", "learned"])
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other scheduler forms")
+    ap.add_argument("--batch-shape", type=int, nargs=2, default=None, metavar=("THREADS", "LANES"),
+                    help="batch4096: use this shape instead of the autotuner's")
     ap.add_argument("--probe", default="auto", choices=["auto", "hash", "bsearch"])
     ap.add_argument("--peel-mode", default="auto", choices=["auto", "sparse", "dense"])
     ap.add_argument("--support", default="auto", choices=["auto", "hash", "bsearch", "merge"])
