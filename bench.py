@@ -167,9 +167,9 @@ def bench_batch(args):
         tune_ms = None
     else:
         blk, lanes, tune_ms = T.truss_batch_autotune(vo, eo, S, D)
-        print("autotune: %d threads x %d lanes (%.1f ms on the batch; tuning took %.1f s)"
+        print("autotune: %d threads x %d entries in flight (%.1f ms on the batch; tuning took %.1f s)"
               % (blk, lanes, tune_ms, time.perf_counter() - t), file=sys.stderr, flush=True)
-    plan = T.BatchPlan(vo, eo, S, D, T.make_options(batch_block=blk, batch_lanes=lanes))
+    plan = T.BatchPlan(vo, eo, S, D, T.make_options(batch_block=blk, batch_ilp=lanes))
     for i in range(args.warmup):
         _, st = plan.run()
         print("warmup %d: %.2f ms" % (i, st["ms_total"]), file=sys.stderr, flush=True)
@@ -215,7 +215,7 @@ def bench_batch(args):
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "batch4096", "description": WORKLOADS["batch4096"], "seed": args.seed,
-                   "graphs": 4096, "m": m, "batch_block": blk, "batch_lanes": lanes},
+                   "graphs": 4096, "m": m, "batch_block": blk, "batch_ilp": lanes},
         "kmax": st["kmax"], "levels": st["levels"], "subrounds": st["subrounds"], "triangles": st["triangles"],
         "support_work": st["support_work"], "peel_work": st["peel_work"], "batch_kernel_ms": kms,
         "autotune_ms": tune_ms,
@@ -260,7 +260,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--scheduler", default="learned", choices=["plain", "heuristic", "learned"])
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other scheduler forms")
-    ap.add_argument("--batch-shape", type=int, nargs=2, default=None, metavar=("THREADS", "LANES"),
+    ap.add_argument("--batch-shape", type=int, nargs=2, default=None, metavar=("THREADS", "ILP"),
                     help="batch4096: use this shape instead of the autotuner's")
     ap.add_argument("--probe", default="auto", choices=["auto", "hash", "bsearch"])
     ap.add_argument("--peel-mode", default="auto", choices=["auto", "sparse", "dense"])

@@ -113,8 +113,8 @@ typedef struct truss_options {
   int64_t max_subrounds;    /* > 0: fail with TRUSS_E_INTERNAL past this many  */
   int32_t grid_blocks;      /* > 0: persistent-kernel workgroups (tuning)      */
   int32_t peel_probe;       /* TRUSS_PROBE_*                                    */
-  int32_t batch_block;      /* truss_batch: threads per workgroup (256, 512, 1024; 0 = 512) */
-  int32_t batch_lanes;      /* truss_batch: lanes per edge walk (1, 4, 16, 64; 0 = 4)       */
+  int32_t batch_block;      /* truss_batch: threads per workgroup (256, 512, 1024; 0 = 1024) */
+  int32_t batch_ilp;        /* truss_batch: walk entries in flight per thread (1, 2, 4; 0 = 2) */
   int32_t reserved[4];
 } truss_options;
 
@@ -200,15 +200,16 @@ int truss_batch_plan_create(int32_t num_graphs, const int64_t *vtx_off, const in
 int truss_batch_plan_run(truss_batch_plan *plan, truss_stats *stats, void *stream);
 void truss_batch_plan_destroy(truss_batch_plan *plan);
 
-/* Autotuner of the batch shape (threads per workgroup x lanes per edge): every
+/* Autotuner of the batch shape (threads per workgroup x walk entries in flight
+ * per thread): every
  * built shape is timed on a size-stratified sample of at most 512 of the
  * batch's graphs, then the three fastest on the whole batch; the fastest of
- * those is returned in *best_block, *best_lanes (host) with its whole-batch
+ * those is returned in *best_block, *best_ilp (host) with its whole-batch
  * time in *best_ms (host, nullable).  Leaves valid truss numbers in truss_out. */
 int truss_batch_autotune(int32_t num_graphs, const int64_t *vtx_off, const int64_t *edge_off,
                          const int32_t *src, const int32_t *dst, int32_t *truss_out,
                          const truss_options *opts, void *ws, size_t ws_bytes, void *stream,
-                         int32_t *best_block, int32_t *best_lanes, float *best_ms);
+                         int32_t *best_block, int32_t *best_ilp, float *best_ms);
 
 /* ---- tracing: the per-decision record behind the learned scheduler ----- */
 /* Peeling level actions: bit 0 = probe (0 hash table, 1 binary search),

@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
                 ("peel_mode", ctypes.c_int32), ("scheduler", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("max_subrounds", ctypes.c_int64),
                 ("grid_blocks", ctypes.c_int32), ("peel_probe", ctypes.c_int32),
-                ("batch_block", ctypes.c_int32), ("batch_lanes", ctypes.c_int32),
+                ("batch_block", ctypes.c_int32), ("batch_ilp", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 4)]
 
 
@@ -206,12 +206,12 @@ class Graph:
 
 def make_options(support_strategy=SUP_AUTO, peel_mode=PEEL_AUTO, scheduler=SCHED_HEURISTIC,
                  model=None, max_subrounds=0, grid_blocks=0, peel_probe=PROBE_AUTO, batch_block=0,
-                 batch_lanes=0):
+                 batch_ilp=0):
     o = Options()
     load_library().truss_default_options(ctypes.byref(o))
     o.support_strategy, o.peel_mode, o.scheduler = support_strategy, peel_mode, scheduler
     o.peel_probe = peel_probe
-    o.batch_block, o.batch_lanes = batch_block, batch_lanes
+    o.batch_block, o.batch_ilp = batch_block, batch_ilp
     o.model = _ptr(model).value if model is not None else None
     o.max_subrounds, o.grid_blocks = max_subrounds, grid_blocks
     return o
@@ -336,7 +336,7 @@ class BatchPlan:
 
 def truss_batch_autotune(vtx_off, edge_off, src, dst, opts: Options | None = None, out=None, ws=None,
                          stream=None):
-    """Fastest (threads per workgroup, lanes per edge) on a sample of the batch,
+    """Fastest (threads per workgroup, walk entries in flight per thread) for the batch,
     and its sample time in ms."""
     torch = _torch()
     lib = load_library()

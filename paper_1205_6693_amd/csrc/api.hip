@@ -73,8 +73,7 @@ int validate_options(const truss_options* o) {
       o->scheduler < TRUSS_SCHED_PLAIN || o->scheduler > TRUSS_SCHED_LEARNED ||
       o->peel_probe < TRUSS_PROBE_AUTO || o->peel_probe > TRUSS_PROBE_BSEARCH ||
       !(o->batch_block == 0 || o->batch_block == 256 || o->batch_block == 512 || o->batch_block == 1024) ||
-      !(o->batch_lanes == 0 || o->batch_lanes == 1 || o->batch_lanes == 4 || o->batch_lanes == 16 ||
-        o->batch_lanes == 64)) {
+      !(o->batch_ilp == 0 || o->batch_ilp == 1 || o->batch_ilp == 2 || o->batch_ilp == 4)) {
     set_last_error("option out of range");
     return TRUSS_E_INVAL;
   }

@@ -16,8 +16,9 @@
 // compute unit; workgroup barriers order its global-memory traffic, and no
 // other workgroup reads it.
 //
-// Shapes: T threads per workgroup and G lanes per edge (the walk of an edge's
-// shorter row and its probes are split over G lanes).  Both are template
+// Shapes: T threads per workgroup and NI walk entries in flight per thread
+// (peeling walks are flattened over the workgroup; each thread advances NI
+// entries step by step so their memory accesses overlap).  Both are template
 // parameters picked by the autotuner.
 #include <string.h>
 
@@ -107,8 +108,19 @@ __device__ __forceinline__ int ldw(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+constexpr int kSweepNI = 4;                    // live-list entries per thread per sweep step
+constexpr int kBitmapWords = 256;              // per wavefront: graphs with up to 8192 vertices
+constexpr int kBitmapBits = kBitmapWords * 32;
+
 template <int T>
 struct Lds {
+  unsigned bits[T / kWave][kBitmapWords];
+  int pre[T / kWave][kWave];
+  int rowst[T / kWave][kWave];
+  int cnt64[T / kWave][kWave];
+  long long wpre[T + 1];  // flattened walk of a frontier chunk: prefix of walk lengths
+  long long wtot[T / kWave];
+  int we[T], wb[T], wra[T], wrb[T], wlb[T];
   int tmp[T / kWave + 2];
   int err;
   int cnt;
@@ -141,6 +153,19 @@ __device__ void block_scan(const int32_t* in, int32_t* out, int n, Lds<T>& L) {
   if (threadIdx.x == 0) out[n] = carry;
 }
 
+// inclusive prefix sum over the workgroup of one value per thread
+template <int T>
+__device__ long long block_scan64(long long v, Lds<T>& L) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  const long long inc = wave_inclusive_sum(v);
+  if (lane == kWave - 1) L.wtot[w] = inc;
+  __syncthreads();
+  long long base = 0;
+  for (int q = 0; q < w; ++q) base += L.wtot[q];
+  __syncthreads();
+  return base + inc;
+}
+
 // slot in an LDS counter for each lane with `want` (one LDS atomic per wavefront)
 __device__ __forceinline__ int lds_append(int* counter, bool want) {
   const uint64_t m = ballot(want);
@@ -163,19 +188,10 @@ __device__ __forceinline__ int row_find(const int32_t* col, int lo, int hi, int 
   return lo;
 }
 
-// sum over the G lanes of a group (G a power of two <= 64)
-template <int G>
-__device__ __forceinline__ int group_sum(int x) {
-#pragma unroll
-  for (int d = G / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-  return x;
-}
-
-template <int T, int G>
+template <int T, int NI>
 __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& L) {
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
-  constexpr int kWavesT = T / kWave, kGroups = T / G;
-  const int grp = tid / G, lg = tid % G;
+  constexpr int kWavesT = T / kWave;
   const int n = (int)(A.vo[g + 1] - A.vo[g]);
   const int m = (int)(A.eo[g + 1] - A.eo[g]);
   const int32_t* src = A.src + A.eo[g];
@@ -265,21 +281,84 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
   // 4. support (Definition 1): each edge walks its shorter endpoint row and
   // looks every neighbour up in the other row
   unsigned long long tri3 = 0, wsup = 0, wpeel = 0;
-  for (int i = grp; i < m; i += kGroups) {
-    const int u = ldw(&S.eu[i]), v = ldw(&S.ev[i]);
-    const int ru = ldw(&S.rp[u]), du = ldw(&S.rp[u + 1]) - ru;
-    const int rv = ldw(&S.rp[v]), dv = ldw(&S.rp[v + 1]) - rv;
-    const bool ua = du < dv || (du == dv && u < v);
-    const int wa = ua ? ru : rv, la = ua ? du : dv;
-    const int wb = ua ? rv : ru, lb = ua ? dv : du;
-    int cnt = 0;
-    for (int j = lg; j < la; j += G) {
-      const int w = ldw(&S.col[wa + j]);
-      const int p = row_find(S.col, wb, wb + lb, w);
-      cnt += (p < wb + lb && ldw(&S.col[p]) == w) ? 1 : 0;
+  if (n <= kBitmapBits) {
+    // the longer endpoint u's row as a bitmap in LDS (a wavefront per u):
+    // every shorter neighbour v walks its row and tests the bits
+    unsigned* bm = L.bits[wv];
+    for (int x = lane; x < kBitmapWords; x += kWave) bm[x] = 0u;
+    wave_sync();
+    for (int u = wv; u < n; u += kWavesT) {
+      const int ru = ldw(&S.rp[u]), du = ldw(&S.rp[u + 1]) - ru;
+      if (du == 0) continue;
+      for (int j = lane; j < du; j += kWave) {
+        const int w = ldw(&S.col[ru + j]);
+        atomicOr(&bm[w >> 5], 1u << (w & 31));
+      }
+      wave_sync();
+      for (int c0 = 0; c0 < du; c0 += kWave) {
+        // shorter neighbours among this 64-entry chunk of the row, their rows flattened
+        const int j = c0 + lane;
+        int v = 0, rv = 0, dv = 0, e = 0;
+        bool shorter = false;
+        if (j < du) {
+          v = ldw(&S.col[ru + j]);
+          e = ldw(&S.eid[ru + j]);
+          rv = ldw(&S.rp[v]);
+          dv = ldw(&S.rp[v + 1]) - rv;
+          shorter = dv < du || (dv == du && v < u);
+        }
+        const int len = shorter ? dv : 0;
+        const int inc = wave_inclusive_sum(len);
+        const int tot = __shfl(inc, kWave - 1, kWave);
+        // the flattened walk: slot q covers [pre[q], pre[q] + len of lane q)
+        // and starts at row offset rowst[q]
+        L.pre[wv][lane] = inc - len;
+        L.rowst[wv][lane] = rv;
+        L.cnt64[wv][lane] = 0;
+        wave_sync();
+        for (int t0 = 0; t0 < tot; t0 += kWave) {
+          const int t = t0 + lane;
+          if (t < tot) {
+            int lo = 0, hi = kWave - 1;  // last slot whose range starts at or before t
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (L.pre[wv][mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int w = ldw(&S.col[L.rowst[wv][lo] + (t - L.pre[wv][lo])]);
+            if (bm[w >> 5] >> (w & 31) & 1u) atomicAdd(&L.cnt64[wv][lo], 1);
+          }
+        }
+        wave_sync();
+        if (shorter) {
+          const int cnt = L.cnt64[wv][lane];
+          S.sup[e] = cnt;
+          S.stamp[e] = 0;
+          tri3 += (unsigned long long)cnt;
+          wsup += (unsigned long long)dv;
+        }
+        wave_sync();
+      }
+      for (int j = lane; j < du; j += kWave) {
+        const int w = ldw(&S.col[ru + j]);
+        bm[w >> 5] = 0u;
+      }
+      wave_sync();
     }
-    cnt = group_sum<G>(cnt);
-    if (lg == 0) {
+  } else {
+    // larger graphs: a thread per edge, binary search of the longer row
+    for (int i = tid; i < m; i += T) {
+      const int u = ldw(&S.eu[i]), v = ldw(&S.ev[i]);
+      const int ru = ldw(&S.rp[u]), du = ldw(&S.rp[u + 1]) - ru;
+      const int rv = ldw(&S.rp[v]), dv = ldw(&S.rp[v + 1]) - rv;
+      const bool ua = du < dv || (du == dv && u < v);
+      const int wa = ua ? ru : rv, la = ua ? du : dv;
+      const int wb = ua ? rv : ru, lb = ua ? dv : du;
+      int cnt = 0;
+      for (int j = 0; j < la; ++j) {
+        const int w = ldw(&S.col[wa + j]);
+        const int p = row_find(S.col, wb, wb + lb, w);
+        cnt += (p < wb + lb && ldw(&S.col[p]) == w) ? 1 : 0;
+      }
       S.sup[i] = cnt;
       S.stamp[i] = 0;
       tri3 += (unsigned long long)cnt;
@@ -296,27 +375,50 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
   int k = 1, r = 0, levels = 0, subrounds = 0;
   __syncthreads();
   for (;;) {
-    // live list of the level and the minimum live support
+    // live list of the level, its minimum support, and at once the live edges
+    // with sup <= k-1: the frontier F_0 of level k+1 (stamped r+1).  If none
+    // is taken, the minimum is at least k and the next level is min + 2.
+    __syncthreads();  // every thread has read the previous level's counters
     if (tid == 0) {
       L.cnt = 0;
       L.minv = kIntMax;
+      L.qn = 0;
     }
     __syncthreads();
+    const int kt = k + 1, st = r + 1;
     int mins = kIntMax;
-    for (int t0 = 0; t0 < acnt; t0 += T) {
-      const int t = t0 + tid;
-      bool live = false;
-      int e = 0;
-      if (t < acnt) {
-        e = first ? t : ldw(&alist[acur][t]);
-        live = ldw(&S.stamp[e]) == 0;
-        if (live) {
-          const int sv = ldw(&S.sup[e]);
-          mins = sv < mins ? sv : mins;
+    for (int t0 = 0; t0 < acnt; t0 += kSweepNI * T) {
+      int e[kSweepNI], sv[kSweepNI], sk[kSweepNI];
+      bool live[kSweepNI], take[kSweepNI];
+#pragma unroll
+      for (int q = 0; q < kSweepNI; ++q) {
+        const int t = t0 + q * T + tid;
+        e[q] = 0;
+        live[q] = t < acnt;
+        if (live[q]) e[q] = first ? t : ldw(&alist[acur][t]);
+      }
+#pragma unroll
+      for (int q = 0; q < kSweepNI; ++q) {
+        sk[q] = live[q] ? ldw(&S.stamp[e[q]]) : 1;
+        sv[q] = live[q] ? ldw(&S.sup[e[q]]) : kIntMax;
+      }
+#pragma unroll
+      for (int q = 0; q < kSweepNI; ++q) {
+        live[q] = live[q] && sk[q] == 0;
+        take[q] = live[q] && sv[q] <= kt - 2;
+        if (live[q]) mins = sv[q] < mins ? sv[q] : mins;
+        if (take[q]) {
+          S.stamp[e[q]] = st;
+          out[e[q]] = kt;
         }
       }
-      const int pos = lds_append(&L.cnt, live);
-      if (live) alist[acur ^ 1][pos] = e;
+#pragma unroll
+      for (int q = 0; q < kSweepNI; ++q) {
+        const int pos = lds_append(&L.cnt, live[q]);
+        if (live[q]) alist[acur ^ 1][pos] = e[q];
+        const int qpos = lds_append(&L.qn, take[q]);
+        if (take[q]) fq[st & 1][qpos] = e[q];
+      }
     }
     mins = wave_min(mins);
     if (lane == 0 && mins != kIntMax) atomicMin(&L.minv, mins);
@@ -325,10 +427,151 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
     acur ^= 1;
     first = false;
     if (acnt == 0) break;
-    if (2 * acnt < csr_live) {
+    ++levels;
+    ++r;
+    if (L.qn > 0) {
+      k = kt;
+    } else {
+      // frontier F_0 of level min + 2: live edges with sup <= k-2 get truss number k
+      k = L.minv + 2;
+      __syncthreads();
+      for (int t0 = 0; t0 < acnt; t0 += T) {
+        const int t = t0 + tid;
+        bool take = false;
+        int e = 0;
+        if (t < acnt) {
+          e = ldw(&alist[acur][t]);
+          take = ldw(&S.sup[e]) <= k - 2;
+          if (take) {
+            S.stamp[e] = r;
+            out[e] = k;
+          }
+        }
+        const int pos = lds_append(&L.qn, take);
+        if (take) fq[r & 1][pos] = e;
+      }
+      __syncthreads();
+    }
+    const int l = k - 2;
+    int qn = L.qn;
+    int removed = qn;
+    while (qn > 0) {
+      ++subrounds;
+      __syncthreads();
+      if (tid == 0) L.qn = 0;
+      __syncthreads();
+      const int32_t* Q = fq[r & 1];
+      int32_t* NQ = fq[(r + 1) & 1];
+      // frontier edges in chunks of T; the chunk's walks (shorter live row of
+      // each edge) are laid end to end and every thread takes NI entries of
+      // the flattened range at a time, so long and short walks share the lanes
+      for (int c0 = 0; c0 < qn; c0 += T) {
+        const int i = c0 + tid;
+        int e = 0, b = 0, ra = 0, la = 0, rb = 0, lb = 0;
+        if (i < qn) {
+          e = ldw(&Q[i]);
+          const int u = ldw(&S.eu[e]), v = ldw(&S.ev[e]);
+          const int ru = ldw(&S.rp[u]), du = ldw(&S.cur[u]);
+          const int rv = ldw(&S.rp[v]), dv = ldw(&S.cur[v]);
+          const bool ua = du < dv || (du == dv && u < v);
+          b = ua ? v : u;
+          ra = ua ? ru : rv;
+          la = ua ? du : dv;
+          rb = ua ? rv : ru;
+          lb = ua ? dv : du;
+          wpeel += (unsigned long long)la;
+        }
+        const long long Wc = block_scan64<T>((long long)la, L);
+        L.wpre[tid + 1] = Wc;
+        if (tid == 0) L.wpre[0] = 0;
+        L.we[tid] = e;
+        L.wb[tid] = b;
+        L.wra[tid] = ra;
+        L.wrb[tid] = rb;
+        L.wlb[tid] = lb;
+        __syncthreads();
+        const long long W = L.wpre[T];
+        for (long long t0 = 0; t0 < W; t0 += (long long)NI * T) {
+          int ee[NI], bb[NI], jj[NI], rbb[NI], lbb[NI], w[NI], e1[NI], s1[NI], e2[NI], s2[NI];
+          bool ok[NI];
+#pragma unroll
+          for (int q = 0; q < NI; ++q) {
+            const long long t = t0 + (long long)q * T + tid;
+            ok[q] = t < W;
+            ee[q] = bb[q] = jj[q] = rbb[q] = lbb[q] = 0;
+            if (ok[q]) {
+              int x = 0, y = T - 1;  // last edge whose range starts at or before t
+              while (x < y) {
+                const int mid = (x + y + 1) >> 1;
+                if (L.wpre[mid] <= t) x = mid; else y = mid - 1;
+              }
+              ee[q] = L.we[x];
+              bb[q] = L.wb[x];
+              jj[q] = L.wra[x] + (int)(t - L.wpre[x]);
+              rbb[q] = L.wrb[x];
+              lbb[q] = L.wlb[x];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < NI; ++q) {
+            w[q] = ok[q] ? ldw(&S.col[jj[q]]) : -1;
+            e1[q] = ok[q] ? ldw(&S.eid[jj[q]]) : 0;
+          }
+#pragma unroll
+          for (int q = 0; q < NI; ++q) {
+            ok[q] = ok[q] && w[q] != bb[q];
+            s1[q] = ok[q] ? ldw(&S.stamp[e1[q]]) : 0;
+          }
+#pragma unroll
+          for (int q = 0; q < NI; ++q) {
+            ok[q] = ok[q] && !removed_at(s1[q], r);
+            e2[q] = 0;
+            if (ok[q]) {
+              const int p = row_find(S.col, rbb[q], rbb[q] + lbb[q], w[q]);
+              if (p < rbb[q] + lbb[q] && ldw(&S.col[p]) == w[q]) e2[q] = ldw(&S.eid[p]);
+              else ok[q] = false;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < NI; ++q) s2[q] = ok[q] ? ldw(&S.stamp[e2[q]]) : 0;
+#pragma unroll
+          for (int q = 0; q < NI; ++q) {
+            int f1 = -1, f2 = -1;
+            const bool live = ok[q] && !removed_at(s2[q], r) && !(s1[q] == r && e1[q] < ee[q]) &&
+                              !(s2[q] == r && e2[q] < ee[q]);
+            if (live && s1[q] != r) {
+              const int old = atomicSub(&S.sup[e1[q]], 1);
+              if (old == l + 1) {
+                S.stamp[e1[q]] = r + 1;
+                out[e1[q]] = k;
+                f1 = e1[q];
+              }
+            }
+            if (live && s2[q] != r) {
+              const int old = atomicSub(&S.sup[e2[q]], 1);
+              if (old == l + 1) {
+                S.stamp[e2[q]] = r + 1;
+                out[e2[q]] = k;
+                f2 = e2[q];
+              }
+            }
+            const int p1 = lds_append(&L.qn, f1 >= 0);
+            if (f1 >= 0) NQ[p1] = f1;
+            const int p2 = lds_append(&L.qn, f2 >= 0);
+            if (f2 >= 0) NQ[p2] = f2;
+          }
+        }
+        __syncthreads();  // the chunk tables are reused by the next chunk
+      }
+      __syncthreads();
+      qn = L.qn;
+      removed += qn;
+      ++r;
+    }
+    if (2 * (acnt - removed) < csr_live) {
       // drop removed entries from the rows once the live edge count has halved
       // (stable, so rows stay sorted; a wavefront per row)
-      csr_live = acnt;
+      csr_live = acnt - removed;
       for (int x = wv; x < n; x += kWavesT) {
         const int base = ldw(&S.rp[x]);
         const int len = ldw(&S.cur[x]);
@@ -355,108 +598,6 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
       }
       __syncthreads();
     }
-    k = L.minv + 2 > k + 1 ? L.minv + 2 : k + 1;
-    const int l = k - 2;
-    ++levels;
-    ++r;
-    // frontier F_0: live edges with sup <= k-2 get truss number k
-    if (tid == 0) L.qn = 0;
-    __syncthreads();
-    for (int t0 = 0; t0 < acnt; t0 += T) {
-      const int t = t0 + tid;
-      bool take = false;
-      int e = 0;
-      if (t < acnt) {
-        e = ldw(&alist[acur][t]);
-        take = ldw(&S.sup[e]) <= l;
-        if (take) {
-          S.stamp[e] = r;
-          out[e] = k;
-        }
-      }
-      const int pos = lds_append(&L.qn, take);
-      if (take) fq[r & 1][pos] = e;
-    }
-    __syncthreads();
-    int qn = L.qn;
-    while (qn > 0) {
-      ++subrounds;
-      __syncthreads();
-      if (tid == 0) L.qn = 0;
-      __syncthreads();
-      const int32_t* Q = fq[r & 1];
-      int32_t* NQ = fq[(r + 1) & 1];
-      for (int f0 = 0; f0 < qn; f0 += kGroups) {
-        const int f = f0 + grp;
-        const bool has = f < qn;
-        int e = 0, b = 0, ra = 0, la = 0, rb = 0, lb = 0;
-        if (has) {
-          e = ldw(&Q[f]);
-          const int u = ldw(&S.eu[e]), v = ldw(&S.ev[e]);
-          const int ru = ldw(&S.rp[u]), du = ldw(&S.cur[u]);
-          const int rv = ldw(&S.rp[v]), dv = ldw(&S.cur[v]);
-          const bool ua = du < dv || (du == dv && u < v);
-          b = ua ? v : u;
-          ra = ua ? ru : rv;
-          la = ua ? du : dv;
-          rb = ua ? rv : ru;
-          lb = ua ? dv : du;
-        }
-        const int trips = has ? (la + G - 1) / G : 0;
-        if (has && lg == 0) wpeel += (unsigned long long)la;
-        // every lane of the wavefront runs the same number of appends
-        int wtrips = trips;
-#pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) {
-          const int y = __shfl_xor(wtrips, d, kWave);
-          wtrips = y > wtrips ? y : wtrips;
-        }
-        for (int it = 0; it < wtrips; ++it) {
-          const int j = it * G + lg;
-          int f1 = -1, f2 = -1;
-          if (it < trips && j < la) {
-            const int w = ldw(&S.col[ra + j]);
-            if (w != b) {
-              const int e1 = ldw(&S.eid[ra + j]);
-              const int s1 = ldw(&S.stamp[e1]);
-              if (!removed_at(s1, r)) {
-                const int p = row_find(S.col, rb, rb + lb, w);
-                if (p < rb + lb && ldw(&S.col[p]) == w) {
-                  const int e2 = ldw(&S.eid[p]);
-                  const int s2 = ldw(&S.stamp[e2]);
-                  const bool own = !((s1 == r && e1 < e) || (s2 == r && e2 < e));
-                  if (!removed_at(s2, r) && own) {
-                    if (s1 != r) {
-                      const int old = atomicSub(&S.sup[e1], 1);
-                      if (old == l + 1) {
-                        S.stamp[e1] = r + 1;
-                        out[e1] = k;
-                        f1 = e1;
-                      }
-                    }
-                    if (s2 != r) {
-                      const int old = atomicSub(&S.sup[e2], 1);
-                      if (old == l + 1) {
-                        S.stamp[e2] = r + 1;
-                        out[e2] = k;
-                        f2 = e2;
-                      }
-                    }
-                  }
-                }
-              }
-            }
-          }
-          const int p1 = lds_append(&L.qn, f1 >= 0);
-          if (f1 >= 0) NQ[p1] = f1;
-          const int p2 = lds_append(&L.qn, f2 >= 0);
-          if (f2 >= 0) NQ[p2] = f2;
-        }
-      }
-      __syncthreads();
-      qn = L.qn;
-      ++r;
-    }
   }
   // per-graph totals
   tri3 = wave_sum(tri3);
@@ -479,7 +620,7 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
   }
 }
 
-template <int T, int G>
+template <int T, int NI>
 __global__ void __launch_bounds__(T) k_batch(BatchArgs A) {
   __shared__ Lds<T> L;
   const Slot S = slot_at(A, blockIdx.x);
@@ -488,7 +629,7 @@ __global__ void __launch_bounds__(T) k_batch(BatchArgs A) {
     __syncthreads();
     const int gi = L.g;
     if (gi >= A.G) break;
-    process_graph<T, G>(A, S, A.order[gi], L);
+    process_graph<T, NI>(A, S, A.order[gi], L);
     __syncthreads();
   }
 }
@@ -513,17 +654,17 @@ __global__ void k_batch_init(BatchCtl* c, int32_t* gerr, int G) {
 
 using BatchKernel = void (*)(BatchArgs);
 
-BatchKernel batch_kernel(int T, int G) {
+BatchKernel batch_kernel(int T, int NI) {
 #define TRUSS_BK(t, g) \
-  if (T == t && G == g) return &k_batch<t, g>;
-  TRUSS_BK(256, 1) TRUSS_BK(256, 4) TRUSS_BK(256, 16) TRUSS_BK(256, 64)
-  TRUSS_BK(512, 1) TRUSS_BK(512, 4) TRUSS_BK(512, 16) TRUSS_BK(512, 64)
-  TRUSS_BK(1024, 1) TRUSS_BK(1024, 4) TRUSS_BK(1024, 16) TRUSS_BK(1024, 64)
+  if (T == t && NI == g) return &k_batch<t, g>;
+  TRUSS_BK(256, 1) TRUSS_BK(256, 2) TRUSS_BK(256, 4)
+  TRUSS_BK(512, 1) TRUSS_BK(512, 2) TRUSS_BK(512, 4)
+  TRUSS_BK(1024, 1) TRUSS_BK(1024, 2) TRUSS_BK(1024, 4)
 #undef TRUSS_BK
   return nullptr;
 }
 
-constexpr int kDefaultT = 512, kDefaultG = 4;
+constexpr int kDefaultT = 1024, kDefaultG = 2;
 
 int device_cus() {
   int dev = 0, cus = 0;
@@ -611,7 +752,7 @@ size_t batch_layout(int32_t G, const BatchSplit& B, char* base, BatchLayout* L) 
 
 int check_cfg(int T, int G) {
   if (!batch_kernel(T, G)) {
-    set_last_error("batch shape %d threads x %d lanes per edge is not built", T, G);
+    set_last_error("batch shape %d threads x %d walk entries per thread is not built", T, G);
     return TRUSS_E_INVAL;
   }
   return TRUSS_OK;
@@ -739,7 +880,7 @@ int plan_build(int32_t G, const int64_t* vo, const int64_t* eo, const int32_t* s
     return TRUSS_E_INVAL;
   }
   p->T = opts && opts->batch_block > 0 ? opts->batch_block : kDefaultT;
-  p->Gl = opts && opts->batch_lanes > 0 ? opts->batch_lanes : kDefaultG;
+  p->Gl = opts && opts->batch_ilp > 0 ? opts->batch_ilp : kDefaultG;
   if ((rc = check_cfg(p->T, p->Gl))) { plan_free(p); return rc; }
   const size_t need = batch_layout(G, p->split, nullptr, nullptr);
   if (!ws || ws_bytes < need) {
@@ -878,8 +1019,8 @@ int truss_batch(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_
 
 int truss_batch_autotune(int32_t num_graphs, const int64_t* vtx_off, const int64_t* edge_off, const int32_t* src,
                          const int32_t* dst, int32_t* truss_out, const truss_options* opts, void* ws, size_t ws_bytes,
-                         void* stream, int32_t* best_block, int32_t* best_lanes, float* best_ms) {
-  if (!best_block || !best_lanes) {
+                         void* stream, int32_t* best_block, int32_t* best_ilp, float* best_ms) {
+  if (!best_block || !best_ilp) {
     set_last_error("NULL output");
     return TRUSS_E_INVAL;
   }
@@ -894,7 +1035,7 @@ int truss_batch_autotune(int32_t num_graphs, const int64_t* vtx_off, const int64
   const size_t stride = q.size() > (size_t)want ? q.size() / want : 1;
   for (size_t i = 0; i < q.size(); i += stride) sample.push_back(q[i]);
   *best_block = kDefaultT;
-  *best_lanes = kDefaultG;
+  *best_ilp = kDefaultG;
   if (best_ms) *best_ms = 0.f;
   if (sample.empty()) {
     plan_free(p);
@@ -923,11 +1064,11 @@ int truss_batch_autotune(int32_t num_graphs, const int64_t* vtx_off, const int64
   };
   // stage 1: every shape on the sample (the first run of each warms the caches)
   TRUSS_HIP(hipMemcpyAsync(p->lay.order, sample.data(), sizeof(int32_t) * sample.size(), hipMemcpyHostToDevice, s));
-  const int Ts[3] = {256, 512, 1024}, Gs[4] = {1, 4, 16, 64};
+  const int Ts[3] = {256, 512, 1024}, Gs[3] = {1, 2, 4};
   struct Cand { float ms; int T, G; };
   std::vector<Cand> cands;
   for (int ti = 0; ti < 3 && !rc; ++ti)
-    for (int gi = 0; gi < 4 && !rc; ++gi) {
+    for (int gi = 0; gi < 3 && !rc; ++gi) {
       float t = 0.f;
       rc = time_shape(Ts[ti], Gs[gi], (int)sample.size(), 2, &t);
       if (!rc) cands.push_back({t, Ts[ti], Gs[gi]});
@@ -944,7 +1085,7 @@ int truss_batch_autotune(int32_t num_graphs, const int64_t* vtx_off, const int64
       if (!rc && (best < 0.f || t < best)) {
         best = t;
         *best_block = cands[c].T;
-        *best_lanes = cands[c].G;
+        *best_ilp = cands[c].G;
       }
     }
   }

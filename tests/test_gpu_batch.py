@@ -13,7 +13,7 @@ from gpu_util import dev, lib, say
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(256, 1), (256, 64), (512, 4), (512, 16), (1024, 1), (1024, 4), (1024, 16), (1024, 64)]
+SHAPES = [(b, i) for b in (256, 512, 1024) for i in (1, 2, 4)]
 
 
 def _clique(k):
@@ -55,7 +55,7 @@ def test_batch_every_shape_matches_oracle():
     ref = _expected(gs)
     for blk, lanes in SHAPES:
         say(f"case: batch shape {blk}x{lanes}, {len(gs)} graphs")
-        got, st = _run(T, gs, batch_block=blk, batch_lanes=lanes)
+        got, st = _run(T, gs, batch_block=blk, batch_ilp=lanes)
         np.testing.assert_array_equal(got, ref)
         assert st["m"] == ref.size and st["kmax"] == max(33, int(ref.max()))
         assert st["triangles"] == sum(oracle.support_fwd(n, s, d)[1] for n, s, d in gs if s.size)
@@ -89,7 +89,7 @@ def test_plan_replays_match_oracle():
     gs = _mixed_batch(9, count=30)
     ref = _expected(gs)
     vo, eo, s, d = graphgen.pack(gs)
-    plan = T.BatchPlan(vo, eo, dev(s), dev(d), T.make_options(batch_block=512, batch_lanes=16))
+    plan = T.BatchPlan(vo, eo, dev(s), dev(d), T.make_options(batch_block=512, batch_ilp=4))
     for rep in range(4):
         say(f"case: plan replay {rep}")
         plan.out.fill_(-1)          # eager work between replays
@@ -119,8 +119,8 @@ def test_autotune_returns_a_built_shape():
     vo, eo, s, d = graphgen.pack(gs)
     say("case: autotune")
     blk, lanes, ms = T.truss_batch_autotune(vo, eo, dev(s), dev(d))
-    assert (blk, lanes) in [(b, g) for b in (256, 512, 1024) for g in (1, 4, 16, 64)] and ms > 0
-    got, _ = _run(T, gs, batch_block=blk, batch_lanes=lanes)
+    assert (blk, lanes) in SHAPES and ms > 0
+    got, _ = _run(T, gs, batch_block=blk, batch_ilp=lanes)
     np.testing.assert_array_equal(got, _expected(gs))
 
 

@@ -46,7 +46,7 @@ def test_version_and_strerror(T):
 
 def test_struct_layouts_match_header(T):
     # sizes of the ABI structs: graph 48 B, options 64 B, stats 208 B (options
-    # keep their size: batch_block and batch_lanes took two reserved words)
+    # keep their size: batch_block and batch_ilp took two reserved words)
     assert ctypes.sizeof(T._Graph) == 48
     assert ctypes.sizeof(T.Options) == 64
     assert ctypes.sizeof(T.Stats) == 208
