@@ -111,6 +111,8 @@ __device__ __forceinline__ int ldw(const int32_t* p) {
 constexpr int kSweepNI = 4;                    // live-list entries per thread per sweep step
 constexpr int kBitmapWords = 256;              // per wavefront: graphs with up to 8192 vertices
 constexpr int kBitmapBits = kBitmapWords * 32;
+constexpr int kStageRow = 4096;                // longest row ranked from an LDS copy
+constexpr int kLongRows = 512;                 // rows longer than kBitmapWords listed per graph
 
 template <int T>
 struct Lds {
@@ -118,6 +120,9 @@ struct Lds {
   int pre[T / kWave][kWave];
   int rowst[T / kWave][kWave];
   int cnt64[T / kWave][kWave];
+  int stage[kStageRow];   // a long row being ranked
+  int longrow[kLongRows];
+  int nlong;
   long long wpre[T + 1];  // flattened walk of a frontier chunk: prefix of walk lengths
   long long wtot[T / kWave];
   int we[T], wb[T], wra[T], wrb[T], wlb[T];
@@ -245,18 +250,22 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
   }
   __syncthreads();
   // 3. rows sorted by neighbour id: each entry's rank in its row is the count
-  // of smaller neighbours; an equal neighbour is a duplicated edge
+  // of smaller neighbours; an equal neighbour is a duplicated edge.  A
+  // wavefront per row: up to 64 entries compared in registers, up to
+  // kBitmapWords staged in the wavefront's LDS; longer rows are listed and
+  // ranked afterwards by the whole workgroup from an LDS copy.
+  if (tid == 0) L.nlong = 0;
+  __syncthreads();
   for (int x = wv; x < n; x += kWavesT) {
     const int base = ldw(&S.rp[x]);
     const int len = ldw(&S.rp[x + 1]) - base;
-    for (int c0 = 0; c0 < len; c0 += kWave) {
-      const int j = c0 + lane;
-      const bool ok = j < len;
-      const int cj = ok ? ldw(&S.colA[base + j]) : kIntMax;
-      const int ej = ok ? ldw(&S.eidA[base + j]) : 0;
+    if (len <= kWave) {
+      const bool ok = lane < len;
+      const int cj = ok ? ldw(&S.colA[base + lane]) : kIntMax;
+      const int ej = ok ? ldw(&S.eidA[base + lane]) : 0;
       int rank = 0, eq = 0;
       for (int t = 0; t < len; ++t) {
-        const int ct = ldw(&S.colA[base + t]);
+        const int ct = __shfl(cj, t, kWave);
         rank += ct < cj;
         eq += ct == cj;
       }
@@ -265,6 +274,67 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
         S.eid[base + rank] = ej;
         if (eq > 1) atomicMin(&L.err, kErrDup);
       }
+    } else if (len <= kBitmapWords) {
+      int* st = reinterpret_cast<int*>(L.bits[wv]);
+      for (int j = lane; j < len; j += kWave) st[j] = ldw(&S.colA[base + j]);
+      wave_sync();
+      for (int j = lane; j < len; j += kWave) {
+        const int cj = st[j];
+        int rank = 0, eq = 0;
+        for (int t = 0; t < len; ++t) {
+          const int ct = st[t];
+          rank += ct < cj;
+          eq += ct == cj;
+        }
+        S.col[base + rank] = cj;
+        S.eid[base + rank] = ldw(&S.eidA[base + j]);
+        if (eq > 1) atomicMin(&L.err, kErrDup);
+      }
+      wave_sync();
+    } else if (lane == 0) {
+      const int q = atomicAdd(&L.nlong, 1);
+      if (q < kLongRows) L.longrow[q] = x;
+    }
+  }
+  __syncthreads();
+  const int nlong = L.nlong < kLongRows ? L.nlong : kLongRows;
+  const bool long_overflow = L.nlong > kLongRows;
+  for (int q = 0; q < nlong + (long_overflow ? 1 : 0); ++q) {
+    // q == nlong (after an overflow of the list): every long row not listed
+    int x0 = 0, x1 = 0;
+    if (q < nlong) {
+      x0 = L.longrow[q];
+      x1 = x0 + 1;
+    } else {
+      x0 = 0;
+      x1 = n;
+    }
+    for (int x = x0; x < x1; ++x) {
+      const int base = ldw(&S.rp[x]);
+      const int len = ldw(&S.rp[x + 1]) - base;
+      if (len <= kBitmapWords) continue;
+      if (q == nlong) {
+        bool listed = false;
+        for (int y = 0; y < nlong; ++y) listed = listed || L.longrow[y] == x;
+        if (listed) continue;
+      }
+      const bool staged = len <= kStageRow;
+      if (staged)
+        for (int j = tid; j < len; j += T) L.stage[j] = ldw(&S.colA[base + j]);
+      __syncthreads();
+      for (int j = tid; j < len; j += T) {
+        const int cj = staged ? L.stage[j] : ldw(&S.colA[base + j]);
+        int rank = 0, eq = 0;
+        for (int t = 0; t < len; ++t) {
+          const int ct = staged ? L.stage[t] : ldw(&S.colA[base + t]);
+          rank += ct < cj;
+          eq += ct == cj;
+        }
+        S.col[base + rank] = cj;
+        S.eid[base + rank] = ldw(&S.eidA[base + j]);
+        if (eq > 1) atomicMin(&L.err, kErrDup);
+      }
+      __syncthreads();
     }
   }
   __syncthreads();
