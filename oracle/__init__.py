@@ -9,6 +9,8 @@ Functions follow Wang & Cheng, "Truss Decomposition in Massive Networks":
   support_fwd                    -- Definition 1 via the triangle counting that
                                     Algorithm 2, Step 2 cites (Section 3.2)
   truss                          -- Definition 2 / truss number via Algorithm 2
+  upper_bound                    -- psi(e) of Procedure 6 (Lemma 2: phi <= psi)
+  top_classes                    -- the top-t k-classes of Algorithm 7 from phi
   csr_to_edges                   -- canonical upper-CSR edge order
 """
 from __future__ import annotations
@@ -54,6 +56,7 @@ def _load():
         for f in (lib.oracle_support_def, lib.oracle_support_fwd):
             f.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i64p]
         lib.oracle_truss.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i32p]
+        lib.oracle_upper_bound.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, i32p]
         for f in (lib.oracle_validate_edges, lib.oracle_validate_csr, lib.oracle_csr_to_edges,
                   lib.oracle_support_def, lib.oracle_support_fwd, lib.oracle_truss):
             f.restype = ctypes.c_int
@@ -140,3 +143,26 @@ def truss(n: int, src, dst):
         if rc:
             raise OracleError(rc)
     return phi[: src.size], int(kmax.value)
+
+
+def upper_bound(n: int, src, dst, sup=None):
+    """psi[m]: min{sup(e), x_u, x_v} + 2 (Procedure 6) for every input edge."""
+    src, dst = _edges(src, dst)
+    if sup is None:
+        sup, _ = support_fwd(n, src, dst)
+    sup = np.ascontiguousarray(sup, dtype=np.int32)
+    psi = np.zeros(max(src.size, 1), dtype=np.int32)
+    if src.size:
+        rc = _load().oracle_upper_bound(n, src.size, src, dst, sup, psi)
+        if rc:
+            raise OracleError(rc)
+    return psi[: src.size]
+
+
+def top_classes(phi, t: int):
+    """The top-t k-classes (Algorithm 7's output) from the truss numbers:
+    phi(e) where phi(e) > k_max - t, 0 elsewhere; and the lowest class kept."""
+    phi = np.asarray(phi, dtype=np.int32)
+    kmax = int(phi.max()) if phi.size else 0
+    kmin = max(2, kmax - t + 1)
+    return np.where(phi >= kmin, phi, 0).astype(np.int32), kmin

@@ -375,3 +375,61 @@ int oracle_truss(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
   adj_free(&g);
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Upper bound of the truss number (Procedure 6, Lemma 2).                   */
+/* ------------------------------------------------------------------------- */
+/* For an end vertex w of e, x_w is the largest x such that at least x edges
+ * incident to w, other than e, have support at least x; then
+ * psi(e) = min{sup(e), x_u, x_v} + 2.  The whole graph is taken as one
+ * neighbourhood subgraph, so every edge is internal.  Per vertex the incident
+ * supports are sorted in descending order; the number of edges other than e
+ * with support >= x is a binary search (minus e itself when sup(e) >= x), and
+ * x_w is the last x for which that number is >= x (it never increases with x),
+ * found by a second binary search over x in [0, deg(w) - 1]. */
+static int cmp_desc_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x < y) - (x > y);
+}
+
+/* entries >= x in the descending array s[0..d) */
+static int64_t count_at_least(const int32_t *s, int64_t d, int32_t x) {
+  int64_t lo = 0, hi = d;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (s[mid] >= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+int oracle_upper_bound(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *sup,
+                       int32_t *psi) {
+  adj_t g;
+  int rc = adj_build(n, m, src, dst, &g);
+  if (rc) return rc;
+  int64_t maxdeg = 0;
+  for (int32_t v = 0; v < n; ++v)
+    if (g.off[v + 1] - g.off[v] > maxdeg) maxdeg = g.off[v + 1] - g.off[v];
+  int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+  if (!s) { adj_free(&g); return -OR_NOMEM; }
+  for (int64_t i = 0; i < m; ++i) psi[i] = sup[i];
+  for (int32_t w = 0; w < n; ++w) {
+    int64_t b = g.off[w], d = g.off[w + 1] - b;
+    for (int64_t j = 0; j < d; ++j) s[j] = sup[g.eid[b + j]];
+    qsort(s, (size_t)d, sizeof(int32_t), cmp_desc_i32);
+    for (int64_t j = 0; j < d; ++j) {
+      int64_t e = g.eid[b + j];
+      int64_t lo = 0, hi = d - 1;
+      while (lo < hi) {
+        int64_t x = (lo + hi + 1) / 2;
+        int64_t c = count_at_least(s, d, (int32_t)x) - (sup[e] >= x ? 1 : 0);
+        if (c >= x) lo = x; else hi = x - 1;
+      }
+      if ((int32_t)lo < psi[e]) psi[e] = (int32_t)lo;
+    }
+  }
+  for (int64_t i = 0; i < m; ++i) psi[i] += 2;
+  free(s);
+  adj_free(&g);
+  return OR_OK;
+}

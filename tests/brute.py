@@ -12,6 +12,9 @@ They share no code with the oracle or with the GPU library:
                          the subset (a union of such subsets is one, so the
                          largest one is their union); exhaustive for m <= 16
   kcore_numbers          core number by repeated min-degree deletion
+  x_brute / psi_brute    Procedure 6 by its words: for each end vertex, try
+                         every x and count the other incident edges with
+                         support >= x
 """
 from __future__ import annotations
 
@@ -120,3 +123,20 @@ def kcore_numbers(n, edges):
 def random_graph(rng, n, p):
     edges = [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p]
     return edges
+
+
+def x_brute(n, edges, sup, i, w):
+    """Largest x such that at least x edges incident to w, other than edge i,
+    have support >= x (Procedure 6, Step 5)."""
+    others = [sup[j] for j, (a, b) in enumerate(edges) if j != i and (a == w or b == w)]
+    best = 0
+    for x in range(len(others) + 1):
+        if sum(1 for s in others if s >= x) >= x:
+            best = x
+    return best
+
+
+def psi_brute(n, edges, sup):
+    """psi(e) = min{sup(e), x_u, x_v} + 2 for every edge (Procedure 6, Step 6)."""
+    return np.array([min(sup[i], x_brute(n, edges, sup, i, u), x_brute(n, edges, sup, i, v)) + 2
+                     for i, (u, v) in enumerate(edges)], dtype=np.int64)

@@ -57,6 +57,62 @@ def test_example4_support():
             assert sup_f[i] == val and sup_d[i] == val
 
 
+def test_example4_upper_bound():
+    """Example 4: x_d = 3 and x_g = 2 for the edge (d,g), so psi((d,g)) = 4;
+    every edge of the 5-class has psi = 5; Example 5: psi((e,d)) = 5."""
+    n, s, d, phi = golden_io.fig2()
+    psi = oracle.upper_bound(n, s, d)
+    sup, _ = oracle.support_fwd(n, s, d)
+    edges = list(zip(s.tolist(), d.tolist()))
+    for q, (u, v), w, val in golden_io.example4():
+        i = golden_io.edge_index(s, d, u, v)
+        if q == "psi":
+            assert psi[i] == val
+        elif q == "x":
+            assert brute.x_brute(n, edges, sup, i, w) == val
+    assert (psi[phi == 5] == 5).all()
+
+
+def test_example5_top_two_classes():
+    """Example 5: the top-2 classes of the Figure 2 graph are the K_5 on
+    {a,b,c,d,e} (the 5-class) and the K_4 on {f,h,i,j} (the 4-class)."""
+    n, s, d, phi = golden_io.fig2()
+    top, kmin = oracle.top_classes(oracle.truss(n, s, d)[0], 2)
+    assert kmin == 4
+    names = "abcdefghijkl"
+    k5 = set(itertools.combinations("abcde", 2))
+    k4 = set(itertools.combinations("fhij", 2))
+    for i, (u, v) in enumerate(zip(s, d)):
+        pair = tuple(sorted((names[u], names[v])))
+        assert top[i] == (5 if pair in k5 else 4 if pair in k4 else 0)
+
+
+def test_upper_bound_brute_and_lemma2():
+    """psi by the oracle equals Procedure 6 evaluated by its words, and
+    phi <= psi <= sup + 2 (Lemma 2) on random graphs."""
+    rng = np.random.default_rng(17)
+    for trial in range(120):
+        n = int(rng.integers(3, 30))
+        edges = brute.random_graph(rng, n, float(rng.uniform(0.1, 0.8)))
+        if not edges:
+            continue
+        s, d = _edges(edges)
+        sup, _ = oracle.support_fwd(n, s, d)
+        psi = oracle.upper_bound(n, s, d)
+        np.testing.assert_array_equal(psi, brute.psi_brute(n, edges, sup))
+        phi, _ = oracle.truss(n, s, d)
+        assert (phi <= psi).all() and (psi <= sup + 2).all() and (psi >= 2).all()
+
+
+def test_upper_bound_closed_forms():
+    """K_k: x = k-2 at both ends, psi = k = phi; a star: psi = 2."""
+    for k in (3, 4, 7, 12):
+        s, d = _edges(list(itertools.combinations(range(k), 2)))
+        assert (oracle.upper_bound(k, s, d) == k).all()
+    s, d = _edges([(0, v) for v in range(1, 40)])
+    assert (oracle.upper_bound(40, s, d) == 2).all()
+
+
 # ---------------------------------------------------------------- closed forms
 
 @pytest.mark.parametrize("k", [3, 4, 5, 8, 13])
