@@ -211,6 +211,25 @@ int truss_batch_autotune(int32_t num_graphs, const int64_t *vtx_off, const int64
                          const truss_options *opts, void *ws, size_t ws_bytes, void *stream,
                          int32_t *best_block, int32_t *best_ilp, float *best_ms);
 
+/* ---- upper bound and top-down classes (Procedure 6, Algorithm 7) -------- */
+/* psi(e) = min{sup(e), x_u, x_v} + 2 for every edge, where x_w is the largest x
+ * such that at least x edges incident to w other than e have support >= x
+ * (Procedure 6, the whole graph as one neighbourhood subgraph); phi(e) <= psi(e)
+ * (Lemma 2).  psi_out (device) int32[m], indexed as in "Output indexing".  The
+ * workspace is truss_workspace_size's. */
+int truss_upper_bound(const truss_graph *g, int32_t *psi_out, void *ws, size_t ws_bytes, void *stream);
+
+/* The top-t k-classes (Algorithm 7's output): truss_out[e] = phi(e) for every
+ * edge with phi(e) > k_max - t, and 0 for the others; *kmin_out = max(2,
+ * k_max - t + 1) and *kmax_out = k_max (host, nullable).  Only the subgraph of
+ * edges with psi(e) >= k is decomposed, for k stepping down from max psi until
+ * k <= k_max - t + 1 (by Lemma 2 that subgraph holds every k-truss).
+ * stats (host, nullable): those of the last subgraph decomposition, with m =
+ * its edge count and launches = the number of subgraphs decomposed. */
+int truss_topdown_workspace_size(const truss_graph *g, const truss_options *opts, size_t *bytes);
+int truss_topdown(const truss_graph *g, int32_t t, int32_t *truss_out, int32_t *kmin_out, int32_t *kmax_out,
+                  const truss_options *opts, truss_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- tracing: the per-decision record behind the learned scheduler ----- */
 /* Peeling level actions: bit 0 = probe (0 hash table, 1 binary search),
  * bit 1 = frontier mode (0 sparse worklist, 1 dense re-scan). */

@@ -9,6 +9,8 @@ Entry points mirror the C ABI in include/truss.h:
     truss_batch(vtx_off, edge_off, src, dst, ...) -> (truss int32[M], stats dict)
     truss_workspace_size(graph)       -> bytes
     truss_decompose_traced(graph, ...) -> (truss, stats, trace dict)
+    truss_upper_bound(graph)          -> psi int32[m] (Procedure 6)
+    truss_topdown(graph, t)           -> (top-t classes int32[m], kmin, kmax, stats)
     mlp_forward / mlp_backward / mlp_train / sched_train -> the scheduler network
 Graphs are built with Graph.from_edges(n, src, dst) or
 Graph.from_csr(n, row_ptr, col) from int32/int64 CUDA tensors.
@@ -118,6 +120,10 @@ def load_library():
     f32, u64, fp = ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)
     szp = ctypes.POINTER(ctypes.c_size_t)
     lib.truss_decompose_traced.argtypes = [gp, vp, op, sp, tp, vp, ctypes.c_size_t, vp]
+    lib.truss_upper_bound.argtypes = [gp, vp, vp, ctypes.c_size_t, vp]
+    lib.truss_topdown_workspace_size.argtypes = [gp, op, szp]
+    lib.truss_topdown.argtypes = [gp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), op, sp, vp,
+                                  ctypes.c_size_t, vp]
     lib.truss_mlp_param_count.argtypes = [i32, i32, i32]
     lib.truss_mlp_workspace_size.argtypes = [i32, i32, i32, i32, szp]
     lib.truss_mlp_forward.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, ctypes.c_size_t, vp]
@@ -131,6 +137,7 @@ def load_library():
     for f in ("truss_workspace_size", "truss_support", "truss_decompose",
               "truss_batch_workspace_size", "truss_batch", "truss_version", "truss_decompose_traced",
               "truss_batch_plan_create", "truss_batch_plan_run", "truss_batch_autotune",
+              "truss_upper_bound", "truss_topdown_workspace_size", "truss_topdown",
               "truss_mlp_param_count", "truss_mlp_workspace_size", "truss_mlp_forward",
               "truss_mlp_backward", "truss_mlp_train", "truss_sched_part_floats",
               "truss_sched_model_floats", "truss_sched_train_workspace_size", "truss_sched_train"):
@@ -469,3 +476,36 @@ def sched_train(kind: int, X, T_ms, H: int = 32, steps: int = 3000, lr: float = 
     _check(lib.truss_sched_train(kind, _ptr(X), _ptr(T_ms), B, H, steps, lr, seed, _ptr(out),
                                  ctypes.byref(loss), _ptr(ws), ws.numel(), _stream(stream)))
     return out, loss.value
+
+
+def truss_upper_bound(graph: Graph, out=None, ws=None, stream=None):
+    """psi(e) = min{sup(e), x_u, x_v} + 2 of every edge (Procedure 6)."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    if ws is None:
+        ws = workspace(graph)
+    g = graph._c()
+    _check(lib.truss_upper_bound(ctypes.byref(g), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def truss_topdown(graph: Graph, t: int, opts: Options | None = None, out=None, ws=None, stream=None):
+    """The top-t k-classes: (phi where phi > kmax - t else 0, kmin, kmax, stats)."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    g = graph._c()
+    if ws is None:
+        b = ctypes.c_size_t(0)
+        _check(lib.truss_topdown_workspace_size(ctypes.byref(g), ctypes.byref(opts) if opts else None,
+                                                ctypes.byref(b)))
+        ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
+    kmin, kmax = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = Stats()
+    _check(lib.truss_topdown(ctypes.byref(g), t, _ptr(out), ctypes.byref(kmin), ctypes.byref(kmax),
+                             ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    return out, kmin.value, kmax.value, st.to_dict()

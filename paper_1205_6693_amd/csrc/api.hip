@@ -141,7 +141,17 @@ struct Plan {
   unsigned long long* d_total = nullptr;
   int2* sr = nullptr;
   int32_t* truss_canon = nullptr;
+  int32_t *h = nullptr, *ch = nullptr, *psi = nullptr;  // upper bound (Procedure 6)
 };
+
+// what run_single produces
+enum Mode { kModeSupport, kModeDecompose, kModeBound };
+
+void take_bound(const truss_graph* g, Arena& a, Plan& p) {
+  p.h = a.take<int32_t>((size_t)g->n + 1);
+  p.ch = a.take<int32_t>((size_t)g->n + 1);
+  p.psi = a.take<int32_t>((size_t)g->m + 1);
+}
 
 // One layout for size queries and runs: header, build, per-edge state, support, peel.
 void layout(const truss_graph* g, Arena& a, Plan& p, DevGraph* dg_for_sizes) {
@@ -150,6 +160,7 @@ void layout(const truss_graph* g, Arena& a, Plan& p, DevGraph* dg_for_sizes) {
   build_workspace(g, a);
   p.sr = a.take<int2>((size_t)g->m + 1);
   p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
+  take_bound(g, a, p);
   DevGraph dg;
   dg.n = g->n;
   dg.m = g->m;
@@ -184,7 +195,7 @@ struct Timer {
 };
 
 // Runs build + support, then either scatters sup (want_truss false) or peels.
-int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* triangles,
+int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles,
                const truss_options* opts_in, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s,
                truss_trace* trace) {
   int rc = check_graph(g);
@@ -227,13 +238,21 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
   tm.mark(1);
   p.sr = a.take<int2>((size_t)g->m + 1);
   p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
+  take_bound(g, a, p);
   rc = compute_support(dg, sp, p.sr, a, s, trace);
   if (rc) return rc;
   tm.mark(2);
   PeelResult pr;
   unsigned long long tot = 0;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p.d_total);
-  if (!want_truss) {
+  if (mode == kModeBound) {
+    compute_upper_bound(dg, p.sr, p.h, p.ch, p.psi, s);
+    if (g->m > 0)
+      hipLaunchKernelGGL(k_scatter_out, dim3(grid_for(g->m)), dim3(kT), 0, s, p.psi, dg.perm, g->m, out);
+    TRUSS_HIP(hipGetLastError());
+    TRUSS_HIP(hipStreamSynchronize(s));
+    tm.mark(3);
+  } else if (mode == kModeSupport) {
     if (g->m > 0)
       hipLaunchKernelGGL(k_scatter_sup, dim3(grid_for(g->m)), dim3(kT), 0, s, p.sr, dg.perm, g->m, out, p.d_total);
     TRUSS_HIP(hipMemcpyAsync(&tot, p.d_total, sizeof(tot), hipMemcpyDeviceToHost, s));
@@ -271,6 +290,214 @@ int run_single(const truss_graph* g, bool want_truss, int32_t* out, int64_t* tri
     for (int b = 0; b < 6; ++b) stats->frontier_hist[b] = pr.hist[b];
     for (int b = 0; b < 6; ++b) stats->ms_phase[b] = pr.phase_ms[b];
     stats->ms_peel_kernel = pr.kernel_ms;
+  }
+  return TRUSS_OK;
+}
+
+// ---- top-down: the top-t k-classes (Algorithm 7) ----------------------------------------
+// Every edge with phi(e) >= k has psi(e) >= k (Lemma 2), so the k-truss of G
+// lies in E_k = {e : psi(e) >= k}; and the k-truss of E_k is a k-truss of G.
+// Hence the truss numbers >= k of G and of the subgraph E_k agree, and the
+// top-t classes come from decomposing E_k for any k <= k_max - t + 1.  k
+// starts at max psi and moves down (by the exact amount once k_max is known,
+// otherwise by doubling steps) until that holds.
+__global__ void k_max_i32(const int32_t* __restrict__ x, int64_t m, int* __restrict__ out) {
+  int v = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    v = x[i] > v ? x[i] : v;
+  v = wave_max(v);
+  if (lane_id() == 0 && v) atomicMax(out, v);
+}
+
+// edges with psi >= k, as an edge list over the same vertex ids
+__global__ void k_select(const int32_t* __restrict__ psi, const int32_t* __restrict__ eu,
+                         const int32_t* __restrict__ ev, int64_t m, int k, int32_t* __restrict__ ssrc,
+                         int32_t* __restrict__ sdst, int32_t* __restrict__ sid, int* __restrict__ count) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool take = e < m && psi[e] >= k;
+  const int pos = wave_append(count, take);
+  if (take) {
+    ssrc[pos] = eu[e];
+    sdst[pos] = ev[e];
+    sid[pos] = (int32_t)e;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ x, int64_t m, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < m) x[i] = v;
+}
+
+// truss numbers of the subgraph at or above kmin, written to the caller's indexing
+__global__ void k_topdown_out(const int32_t* __restrict__ sub_out, const int32_t* __restrict__ sid, int64_t cnt,
+                              int kmin, const int32_t* __restrict__ perm, int32_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int v = sub_out[i];
+  if (v >= kmin) {
+    const int32_t e = sid[i];
+    out[perm ? perm[e] : e] = v;
+  }
+}
+
+struct TopDownBufs {
+  int* d_scalar;
+  int32_t *ssrc, *sdst, *sid, *sout;
+  char* sub_ws;
+  size_t sub_ws_bytes;
+};
+
+size_t topdown_layout(const truss_graph* g, const truss_options* opts, Arena& a, Plan* p, TopDownBufs* b) {
+  Plan dummy;
+  layout(g, a, p ? *p : dummy, nullptr);
+  TopDownBufs t;
+  t.d_scalar = a.take<int>(64);
+  t.ssrc = a.take<int32_t>((size_t)g->m + 1);
+  t.sdst = a.take<int32_t>((size_t)g->m + 1);
+  t.sid = a.take<int32_t>((size_t)g->m + 1);
+  t.sout = a.take<int32_t>((size_t)g->m + 1);
+  truss_graph sg;
+  memset(&sg, 0, sizeof(sg));
+  sg.fmt = TRUSS_FMT_EDGES;
+  sg.n = g->n;
+  sg.m = g->m;
+  sg.src = sg.dst = reinterpret_cast<const int32_t*>(1);
+  Arena sa;
+  sa.counting = true;
+  Plan sp;
+  layout(&sg, sa, sp, nullptr);
+  t.sub_ws_bytes = sa.used;
+  t.sub_ws = a.take<char>(sa.used);
+  if (b) *b = t;
+  (void)opts;
+  return a.used;
+}
+
+int run_topdown(const truss_graph* g, int32_t t, int32_t* out, int32_t* kmin_out, int32_t* kmax_out,
+                const truss_options* opts, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if ((rc = validate_options(opts))) return rc;
+  if (t < 1) { set_last_error("t must be at least 1"); return TRUSS_E_INVAL; }
+  if (g->m > 0 && !out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
+  Arena need;
+  need.counting = true;
+  const size_t bytes = topdown_layout(g, opts, need, nullptr, nullptr);
+  if (!ws || ws_bytes < bytes) {
+    set_last_error("workspace of %zu bytes given, %zu needed", ws_bytes, bytes);
+    return TRUSS_E_WORKSPACE;
+  }
+  if (kmin_out) *kmin_out = 0;
+  if (kmax_out) *kmax_out = 0;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (g->m == 0) return TRUSS_OK;
+  // main region: build, support, upper bound (the same carving order as layout())
+  Arena a;
+  a.base = static_cast<char*>(ws);
+  a.cap = ws_bytes;
+  Plan p;
+  p.d_err = a.take<int>(64);
+  p.d_total = a.take<unsigned long long>(8);
+  SupPlan sp;
+  PeelPlan pp;
+  int fallback = 0;
+  resolve(opts, &sp, &pp, &fallback, s);
+  Timer tm(stats != nullptr, s);
+  tm.mark(0);
+  DevGraph dg;
+  rc = build_graph(g, a, dg, p.d_err, s);
+  if (rc) return rc;
+  p.sr = a.take<int2>((size_t)g->m + 1);
+  p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
+  take_bound(g, a, p);
+  rc = compute_support(dg, sp, p.sr, a, s, nullptr);
+  if (rc) return rc;
+  compute_upper_bound(dg, p.sr, p.h, p.ch, p.psi, s);
+  // the top-down region follows the whole single-graph layout
+  Arena full;
+  full.counting = true;
+  Plan dummy;
+  layout(g, full, dummy, nullptr);
+  Arena b;
+  b.base = static_cast<char*>(ws) + full.used;
+  b.cap = ws_bytes - full.used;
+  TopDownBufs tb;
+  tb.d_scalar = b.take<int>(64);
+  tb.ssrc = b.take<int32_t>((size_t)g->m + 1);
+  tb.sdst = b.take<int32_t>((size_t)g->m + 1);
+  tb.sid = b.take<int32_t>((size_t)g->m + 1);
+  tb.sout = b.take<int32_t>((size_t)g->m + 1);
+  {
+    truss_graph sg;
+    memset(&sg, 0, sizeof(sg));
+    sg.fmt = TRUSS_FMT_EDGES;
+    sg.n = g->n;
+    sg.m = g->m;
+    sg.src = sg.dst = reinterpret_cast<const int32_t*>(1);
+    Arena sa;
+    sa.counting = true;
+    Plan sp2;
+    layout(&sg, sa, sp2, nullptr);
+    tb.sub_ws_bytes = sa.used;
+    tb.sub_ws = b.take<char>(sa.used);
+  }
+  const unsigned gm = grid_for(g->m);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, tb.d_scalar, (int64_t)64, 0);
+  hipLaunchKernelGGL(k_max_i32, dim3(1024), dim3(kT), 0, s, p.psi, g->m, tb.d_scalar);
+  int psimax = 0;
+  TRUSS_HIP(hipMemcpyAsync(&psimax, tb.d_scalar, sizeof(int), hipMemcpyDeviceToHost, s));
+  TRUSS_HIP(hipStreamSynchronize(s));
+  int k = psimax, step = 1, iters = 0, kmax = 0, cnt = 0;
+  truss_stats sst;
+  memset(&sst, 0, sizeof(sst));
+  for (;;) {
+    ++iters;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, tb.d_scalar, (int64_t)64, 0);
+    hipLaunchKernelGGL(k_select, dim3(gm), dim3(kT), 0, s, p.psi, dg.eu, dg.ev, g->m, k, tb.ssrc, tb.sdst, tb.sid,
+                       tb.d_scalar);
+    TRUSS_HIP(hipMemcpyAsync(&cnt, tb.d_scalar, sizeof(int), hipMemcpyDeviceToHost, s));
+    TRUSS_HIP(hipStreamSynchronize(s));
+    truss_graph sg;
+    memset(&sg, 0, sizeof(sg));
+    sg.fmt = TRUSS_FMT_EDGES;
+    sg.n = g->n;
+    sg.m = cnt;
+    sg.src = tb.ssrc;
+    sg.dst = tb.sdst;
+    rc = run_single(&sg, kModeDecompose, tb.sout, nullptr, opts, &sst, tb.sub_ws, tb.sub_ws_bytes, s, nullptr);
+    if (rc) return rc;
+    const int km = cnt > 0 ? sst.kmax : 0;
+    if (km >= k) {
+      kmax = km;
+      const int kmin = kmax - t + 1 > 2 ? kmax - t + 1 : 2;
+      if (k <= kmin) break;
+      k = kmin;  // one more pass covers every class from kmin up
+    } else if (k <= 2) {
+      kmax = km;
+      break;
+    } else {
+      k = k - step > 2 ? k - step : 2;
+      step *= 2;
+    }
+  }
+  const int kmin = kmax - t + 1 > 2 ? kmax - t + 1 : 2;
+  hipLaunchKernelGGL(k_fill_i32, dim3(gm), dim3(kT), 0, s, out, g->m, 0);
+  if (cnt > 0)
+    hipLaunchKernelGGL(k_topdown_out, dim3(grid_for(cnt)), dim3(kT), 0, s, tb.sout, tb.sid, (int64_t)cnt, kmin,
+                       dg.perm, out);
+  TRUSS_HIP(hipGetLastError());
+  tm.mark(1);
+  TRUSS_HIP(hipStreamSynchronize(s));
+  if (kmin_out) *kmin_out = kmin;
+  if (kmax_out) *kmax_out = kmax;
+  if (stats) {
+    *stats = sst;
+    stats->n = g->n;
+    stats->m = cnt;  // edges of the subgraph decomposed last
+    stats->kmax = kmax;
+    stats->launches = iters;  // subgraph decompositions
+    stats->ms_total = tm.ms(0, 1);
+    stats->sched_fallback = fallback;
   }
   return TRUSS_OK;
 }
@@ -326,20 +553,42 @@ int truss_support(const truss_graph* g, int32_t* sup_out, int64_t* triangles, vo
                   void* stream) {
   if (triangles) *triangles = 0;
   if (g && g->m > 0 && !sup_out) { set_last_error("sup_out is NULL"); return TRUSS_E_INVAL; }
-  return run_single(g, false, sup_out, triangles, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, nullptr);
+  return run_single(g, kModeSupport, sup_out, triangles, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream,
+                    nullptr);
 }
 
 int truss_decompose(const truss_graph* g, int32_t* truss_out, const truss_options* opts, truss_stats* stats,
                     void* ws, size_t ws_bytes, void* stream) {
   if (g && g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
-  return run_single(g, true, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, nullptr);
+  return run_single(g, kModeDecompose, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int truss_decompose_traced(const truss_graph* g, int32_t* truss_out, const truss_options* opts, truss_stats* stats,
                            truss_trace* trace, void* ws, size_t ws_bytes, void* stream) {
   if (!trace) { set_last_error("trace is NULL"); return TRUSS_E_INVAL; }
   if (g && g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
-  return run_single(g, true, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, trace);
+  return run_single(g, kModeDecompose, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, trace);
+}
+
+int truss_upper_bound(const truss_graph* g, int32_t* psi_out, void* ws, size_t ws_bytes, void* stream) {
+  if (g && g->m > 0 && !psi_out) { set_last_error("psi_out is NULL"); return TRUSS_E_INVAL; }
+  return run_single(g, kModeBound, psi_out, nullptr, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+int truss_topdown_workspace_size(const truss_graph* g, const truss_options* opts, size_t* bytes) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if ((rc = validate_options(opts))) return rc;
+  if (!bytes) { set_last_error("bytes is NULL"); return TRUSS_E_INVAL; }
+  Arena a;
+  a.counting = true;
+  *bytes = topdown_layout(g, opts, a, nullptr, nullptr);
+  return TRUSS_OK;
+}
+
+int truss_topdown(const truss_graph* g, int32_t t, int32_t* truss_out, int32_t* kmin_out, int32_t* kmax_out,
+                  const truss_options* opts, truss_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  return run_topdown(g, t, truss_out, kmin_out, kmax_out, opts, stats, ws, ws_bytes, (hipStream_t)stream);
 }
 
 const char* truss_strerror(int code) {

@@ -108,6 +108,10 @@ size_t peel_workspace(const DevGraph& dg, Arena& a);
 int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_canon, Arena& a,
          PeelResult* res, hipStream_t s, truss_trace* trace);
 
+// Upper bound psi(e) (Procedure 6) for every canonical edge; sr holds sup.
+// h, ch: n entries of scratch each; psi: m entries.
+void compute_upper_bound(const DevGraph& dg, const int2* sr, int32_t* h, int32_t* ch, int32_t* psi, hipStream_t s);
+
 void set_last_error(const char* fmt, ...);
 int validate_options(const truss_options* o);  // TRUSS_OK or TRUSS_E_INVAL (message set)
 int device_grid_blocks(const void* kernel, int block, size_t lds);

@@ -80,10 +80,11 @@ def main(name):
     t0 = time.time()
     sup, tri = oracle.support_fwd(n, s, d)
     phi, kmax = oracle.truss(n, s, d)
+    psi = oracle.upper_bound(n, s, d, sup)
     hist = np.bincount(phi, minlength=kmax + 1)
     lines = [
         "# Oracle results for workload %s (seed 1), canonical edge order." % name,
-        "# Written by tests/golden/make_golden.py from oracle.support_fwd and oracle.truss",
+        "# Written by tests/golden/make_golden.py from oracle.support_fwd, oracle.truss and oracle.upper_bound",
         "# (%.0f s on one core)." % (time.time() - t0),
         "n: %d" % n,
         "m: %d" % s.size,
@@ -91,6 +92,7 @@ def main(name):
         "kmax: %d" % kmax,
         "truss_sha256: %s" % digest(phi),
         "support_sha256: %s" % digest(sup),
+        "psi_sha256: %s" % digest(psi),
         "class_sizes: %s" % " ".join("%d:%d" % (k, c) for k, c in enumerate(hist) if c),
     ]
     path = os.path.join(HERE, "oracle_%s.txt" % name)

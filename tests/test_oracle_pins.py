@@ -319,5 +319,6 @@ def test_stored_oracle_records(name):
     assert tri == rec["triangles"] and kmax == rec["kmax"]
     assert golden_io.int32_digest(sup) == rec["support_sha256"]
     assert golden_io.int32_digest(phi) == rec["truss_sha256"]
+    assert golden_io.int32_digest(oracle.upper_bound(n, s, d, sup)) == rec["psi_sha256"]
     hist = np.bincount(phi)
     assert {k: int(c) for k, c in enumerate(hist) if c} == rec["class_sizes"]
