@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--scheduler", default="learned", choices=["plain", "heuristic", "learned"])
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other scheduler forms")
+    ap.add_argument("--topdown", type=int, default=0, metavar="T",
+                    help="also time the top-T k-classes (upper bound + top-down) against the full decomposition")
     ap.add_argument("--batch-shape", type=int, nargs=2, default=None, metavar=("THREADS", "ILP"),
                     help="batch4096: use this shape instead of the autotuner's")
     ap.add_argument("--probe", default="auto", choices=["auto", "hash", "bsearch"])
@@ -400,6 +402,26 @@ def main():
     result["forms"] = forms
     if "plain" in forms and "learned" in forms:
         result["learned_over_plain"] = forms["learned"]["edges_per_s"] / forms["plain"]["edges_per_s"]
+    if args.topdown > 0:
+        tws = None
+        for _ in range(args.warmup):
+            top, kmin, kmax, tst = T.truss_topdown(g, args.topdown, opts, ws=tws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            top, kmin, kmax, tst = T.truss_topdown(g, args.topdown, opts, ws=tws)
+        torch.cuda.synchronize()
+        td_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        t1 = time.perf_counter()
+        T.truss_upper_bound(g, ws=ws)
+        torch.cuda.synchronize()
+        ub_ms = (time.perf_counter() - t1) * 1e3
+        result["topdown"] = {"t": args.topdown, "ms_per_call": td_ms, "kmin": kmin, "kmax": kmax,
+                             "subgraph_m": tst["m"], "decompositions": tst["launches"],
+                             "edges_in_top_classes": int((top > 0).sum().item()),
+                             "full_over_topdown": ms_per_step / td_ms, "upper_bound_ms": ub_ms}
+        print("top-%d classes: %.2f ms (k %d..%d, last subgraph %d edges, %d decompositions)"
+              % (args.topdown, td_ms, kmin, kmax, tst["m"], tst["launches"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale, args.seed)

@@ -3,6 +3,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "common.hpp"
 #include "internal.hpp"
 #include "mlp.hpp"
@@ -246,7 +248,10 @@ int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles
   unsigned long long tot = 0;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p.d_total);
   if (mode == kModeBound) {
-    compute_upper_bound(dg, p.sr, p.h, p.ch, p.psi, s);
+    // the counters of long rows live in the (unused) peeling region
+    int32_t* hs = a.take<int32_t>((size_t)(2 * g->m + g->n + 1));
+    if (a.overflow()) { set_last_error("workspace too small for the upper bound"); return TRUSS_E_WORKSPACE; }
+    compute_upper_bound(dg, p.sr, p.h, p.ch, p.psi, hs, s);
     if (g->m > 0)
       hipLaunchKernelGGL(k_scatter_out, dim3(grid_for(g->m)), dim3(kT), 0, s, p.psi, dg.perm, g->m, out);
     TRUSS_HIP(hipGetLastError());
@@ -340,8 +345,26 @@ __global__ void k_topdown_out(const int32_t* __restrict__ sub_out, const int32_t
   }
 }
 
+// histogram of psi (hist zeroed, psimax + 1 bins); small values counted in LDS first
+constexpr int kHistLds = 2048;
+__global__ void __launch_bounds__(kT) k_psi_hist(const int32_t* __restrict__ psi, int64_t m,
+                                                 int32_t* __restrict__ hist) {
+  __shared__ int lh[kHistLds];
+  for (int b = threadIdx.x; b < kHistLds; b += blockDim.x) lh[b] = 0;
+  __syncthreads();
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int p = psi[e];
+    if (p < kHistLds) atomicAdd(&lh[p], 1);
+    else atomicAdd(&hist[p], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kHistLds; b += blockDim.x)
+    if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
 struct TopDownBufs {
   int* d_scalar;
+  int32_t* hist;
   int32_t *ssrc, *sdst, *sid, *sout;
   char* sub_ws;
   size_t sub_ws_bytes;
@@ -352,6 +375,7 @@ size_t topdown_layout(const truss_graph* g, const truss_options* opts, Arena& a,
   layout(g, a, p ? *p : dummy, nullptr);
   TopDownBufs t;
   t.d_scalar = a.take<int>(64);
+  t.hist = a.take<int32_t>((size_t)g->n + 3);
   t.ssrc = a.take<int32_t>((size_t)g->m + 1);
   t.sdst = a.take<int32_t>((size_t)g->m + 1);
   t.sid = a.take<int32_t>((size_t)g->m + 1);
@@ -412,7 +436,11 @@ int run_topdown(const truss_graph* g, int32_t t, int32_t* out, int32_t* kmin_out
   take_bound(g, a, p);
   rc = compute_support(dg, sp, p.sr, a, s, nullptr);
   if (rc) return rc;
-  compute_upper_bound(dg, p.sr, p.h, p.ch, p.psi, s);
+  {
+    int32_t* hs = a.take<int32_t>((size_t)(2 * g->m + g->n + 1));
+    if (a.overflow()) { set_last_error("workspace too small for the upper bound"); return TRUSS_E_WORKSPACE; }
+    compute_upper_bound(dg, p.sr, p.h, p.ch, p.psi, hs, s);
+  }
   // the top-down region follows the whole single-graph layout
   Arena full;
   full.counting = true;
@@ -423,6 +451,7 @@ int run_topdown(const truss_graph* g, int32_t t, int32_t* out, int32_t* kmin_out
   b.cap = ws_bytes - full.used;
   TopDownBufs tb;
   tb.d_scalar = b.take<int>(64);
+  tb.hist = b.take<int32_t>((size_t)g->n + 3);
   tb.ssrc = b.take<int32_t>((size_t)g->m + 1);
   tb.sdst = b.take<int32_t>((size_t)g->m + 1);
   tb.sid = b.take<int32_t>((size_t)g->m + 1);
@@ -447,7 +476,25 @@ int run_topdown(const truss_graph* g, int32_t t, int32_t* out, int32_t* kmin_out
   int psimax = 0;
   TRUSS_HIP(hipMemcpyAsync(&psimax, tb.d_scalar, sizeof(int), hipMemcpyDeviceToHost, s));
   TRUSS_HIP(hipStreamSynchronize(s));
-  int k = psimax, step = 1, iters = 0, kmax = 0, cnt = 0;
+  // |E_k| for every k from the histogram of psi (psi <= max sup + 2 <= n + 1)
+  std::vector<int64_t> ek((size_t)psimax + 2, 0);
+  {
+    std::vector<int32_t> hh((size_t)psimax + 1, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((psimax + kT) / kT)), dim3(kT), 0, s, tb.hist,
+                       (int64_t)psimax + 1, 0);
+    hipLaunchKernelGGL(k_psi_hist, dim3(1024), dim3(kT), 0, s, p.psi, g->m, tb.hist);
+    TRUSS_HIP(hipMemcpyAsync(hh.data(), tb.hist, sizeof(int32_t) * ((size_t)psimax + 1), hipMemcpyDeviceToHost, s));
+    TRUSS_HIP(hipStreamSynchronize(s));
+    for (int q = psimax; q >= 0; --q) ek[q] = ek[q + 1] + hh[q];
+  }
+  // largest k' <= kcap with |E_k'| >= size (2 if none)
+  auto pick = [&](int kcap, int64_t size) {
+    for (int q = kcap; q > 2; --q)
+      if (ek[q] >= size) return q;
+    return 2;
+  };
+  int64_t want = ek[psimax] > (1 << 17) ? ek[psimax] : (1 << 17);
+  int k = pick(psimax, want), iters = 0, kmax = 0, cnt = 0;
   truss_stats sst;
   memset(&sst, 0, sizeof(sst));
   for (;;) {
@@ -468,16 +515,18 @@ int run_topdown(const truss_graph* g, int32_t t, int32_t* out, int32_t* kmin_out
     if (rc) return rc;
     const int km = cnt > 0 ? sst.kmax : 0;
     if (km >= k) {
+      // k <= k_max: the classes >= k are exact; one more pass if k is above k_max - t + 1
       kmax = km;
       const int kmin = kmax - t + 1 > 2 ? kmax - t + 1 : 2;
       if (k <= kmin) break;
-      k = kmin;  // one more pass covers every class from kmin up
+      k = kmin;
     } else if (k <= 2) {
       kmax = km;
       break;
     } else {
-      k = k - step > 2 ? k - step : 2;
-      step *= 2;
+      // no k-truss: grow the subgraph about fourfold
+      want = 4 * (ek[k] > 1 ? ek[k] : 1);
+      k = pick(k - 1, want);
     }
   }
   const int kmin = kmax - t + 1 > 2 ? kmax - t + 1 : 2;

@@ -109,8 +109,9 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
          PeelResult* res, hipStream_t s, truss_trace* trace);
 
 // Upper bound psi(e) (Procedure 6) for every canonical edge; sr holds sup.
-// h, ch: n entries of scratch each; psi: m entries.
-void compute_upper_bound(const DevGraph& dg, const int2* sr, int32_t* h, int32_t* ch, int32_t* psi, hipStream_t s);
+// h, ch: n entries of scratch each; psi: m entries; hs: 2m + n + 1 entries.
+void compute_upper_bound(const DevGraph& dg, const int2* sr, int32_t* h, int32_t* ch, int32_t* psi, int32_t* hs,
+                         hipStream_t s);
 
 void set_last_error(const char* fmt, ...);
 int validate_options(const truss_options* o);  // TRUSS_OK or TRUSS_E_INVAL (message set)
