@@ -39,14 +39,18 @@ def test_upper_bound_matches_oracle():
         np.testing.assert_array_equal(got, oracle.upper_bound(n, cs, cd))
 
 
-@pytest.mark.parametrize("name", ["er2000", "rmat16"])
+FULL = {"er2000": lambda: graphgen.er_small(1), "rmat16": lambda: graphgen.rmat(16, 16, 1),
+        "rmat20": lambda: graphgen.rmat20(1)}
+
+
+@pytest.mark.parametrize("name", list(FULL))
 def test_upper_bound_full_size(name):
     rec = golden_io.oracle_record(name)
     if rec is None or "psi_sha256" not in rec:
         pytest.skip("no psi record for " + name)
     T = lib()
     say(f"case: psi full size {name}")
-    n, s, d = graphgen.er_small(1) if name == "er2000" else graphgen.rmat(16, 16, 1)
+    n, s, d = FULL[name]()
     got = T.truss_upper_bound(csr_graph(n, s, d)).cpu().numpy()
     assert golden_io.int32_digest(got) == rec["psi_sha256"]
 
