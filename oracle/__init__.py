@@ -11,6 +11,8 @@ Functions follow Wang & Cheng, "Truss Decomposition in Massive Networks":
   truss                          -- Definition 2 / truss number via Algorithm 2
   upper_bound                    -- psi(e) of Procedure 6 (Lemma 2: phi <= psi)
   top_classes                    -- the top-t k-classes of Algorithm 7 from phi
+  core_numbers                   -- core number of every vertex (Section 7)
+  cohesion                       -- Table 6's statistics of the k_max-truss and c_max-core
   csr_to_edges                   -- canonical upper-CSR edge order
 """
 from __future__ import annotations
@@ -57,6 +59,9 @@ def _load():
             f.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i64p]
         lib.oracle_truss.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i32p]
         lib.oracle_upper_bound.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, i32p]
+        lib.oracle_core_numbers.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i32p]
+        lib.oracle_cohesion.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, i32p,
+                                        np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")]
         for f in (lib.oracle_validate_edges, lib.oracle_validate_csr, lib.oracle_csr_to_edges,
                   lib.oracle_support_def, lib.oracle_support_fwd, lib.oracle_truss):
             f.restype = ctypes.c_int
@@ -166,3 +171,33 @@ def top_classes(phi, t: int):
     kmax = int(phi.max()) if phi.size else 0
     kmin = max(2, kmax - t + 1)
     return np.where(phi >= kmin, phi, 0).astype(np.int32), kmin
+
+
+def core_numbers(n: int, src, dst):
+    """(core[n], c_max): the core number of every vertex."""
+    src, dst = _edges(src, dst)
+    rc = _load().oracle_validate_edges(n, src.size, src, dst)
+    if rc:
+        raise OracleError(rc)
+    core = np.zeros(max(n, 1), dtype=np.int32)
+    cmax = ctypes.c_int32(0)
+    rc = _load().oracle_core_numbers(n, src.size, src, dst, core, ctypes.byref(cmax))
+    if rc:
+        raise OracleError(rc)
+    return core[:n], int(cmax.value)
+
+
+def cohesion(n: int, src, dst, phi=None, core=None):
+    """Table 6's columns: dict with V_T, E_T, kmax, CC_T, V_C, E_C, cmax, CC_C."""
+    src, dst = _edges(src, dst)
+    if phi is None:
+        phi, _ = truss(n, src, dst)
+    if core is None:
+        core, _ = core_numbers(n, src, dst)
+    out = np.zeros(8, dtype=np.float64)
+    rc = _load().oracle_cohesion(n, src.size, src, dst, np.ascontiguousarray(phi, dtype=np.int32),
+                                 np.ascontiguousarray(core, dtype=np.int32), out)
+    if rc:
+        raise OracleError(rc)
+    keys = ["V_T", "E_T", "kmax", "CC_T", "V_C", "E_C", "cmax", "CC_C"]
+    return {k: (float(v) if k.startswith("CC") else int(v)) for k, v in zip(keys, out)}

@@ -433,3 +433,136 @@ int oracle_upper_bound(int32_t n, int64_t m, const int32_t *src, const int32_t *
   adj_free(&g);
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Core numbers and the cohesion statistics of the k_max-truss and the       */
+/* c_max-core (Section 7, Table 6).                                          */
+/* ------------------------------------------------------------------------- */
+/* core[v] = the largest c such that v lies in the c-core (the largest
+ * subgraph with minimum degree >= c).  Vertices are kept in buckets by
+ * current degree and taken in order of increasing degree; taking v removes
+ * its edges, which lowers each later neighbour's degree by one and moves it
+ * one bucket down (the bucket method of Batagelj and Zaversnik, 2003). */
+int oracle_core_numbers(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t *core,
+                        int32_t *cmax_out) {
+  adj_t g;
+  int rc = adj_build(n, m, src, dst, &g);
+  if (rc) return rc;
+  int64_t md = 0;
+  int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t *vert = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  if (!deg || !pos || !vert) { free(deg); free(pos); free(vert); adj_free(&g); return -OR_NOMEM; }
+  for (int32_t v = 0; v < n; ++v) {
+    deg[v] = g.off[v + 1] - g.off[v];
+    if (deg[v] > md) md = deg[v];
+  }
+  int64_t *bin = (int64_t *)calloc((size_t)md + 2, sizeof(int64_t));
+  if (!bin) { free(deg); free(pos); free(vert); adj_free(&g); return -OR_NOMEM; }
+  for (int32_t v = 0; v < n; ++v) bin[deg[v]]++;
+  for (int64_t d = 0, start = 0; d <= md; ++d) {  /* bucket starts */
+    int64_t c = bin[d];
+    bin[d] = start;
+    start += c;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    pos[v] = bin[deg[v]]++;
+    vert[pos[v]] = v;
+  }
+  for (int64_t d = md; d > 0; --d) bin[d] = bin[d - 1];
+  bin[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t v = vert[i];
+    for (int64_t j = g.off[v]; j < g.off[v + 1]; ++j) {
+      int32_t u = g.nbr[j];
+      if (deg[u] > deg[v]) {
+        /* swap u with the first vertex of its bucket, then shrink the bucket */
+        int64_t du = deg[u], pu = pos[u], pw = bin[du];
+        int32_t w = vert[pw];
+        if (u != w) {
+          pos[u] = pw; vert[pw] = u;
+          pos[w] = pu; vert[pu] = w;
+        }
+        bin[du]++;
+        deg[u]--;
+      }
+    }
+  }
+  int32_t cmax = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    core[v] = (int32_t)deg[v];
+    if (core[v] > cmax) cmax = core[v];
+  }
+  if (cmax_out) *cmax_out = cmax;
+  free(bin); free(deg); free(pos); free(vert);
+  adj_free(&g);
+  return OR_OK;
+}
+
+/* Statistics of the subgraph S given by a mask over the edges: out[0] = its
+ * vertices (those touching an edge of S), out[1] = its edges, out[2] = the
+ * mean over those vertices of the local clustering coefficient within S:
+ * triangles of S at v divided by deg_S(v)(deg_S(v)-1)/2 (0 when deg_S < 2).
+ * Triangles at v are counted by merging the sorted S-neighbour lists of the
+ * two ends of each S-edge at v. */
+static int subgraph_stats(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const uint8_t *in,
+                          double *out) {
+  int64_t ms = 0;
+  for (int64_t i = 0; i < m; ++i) ms += in[i];
+  int32_t *s2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ms + 1));
+  int32_t *d2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ms + 1));
+  if (!s2 || !d2) { free(s2); free(d2); return -OR_NOMEM; }
+  for (int64_t i = 0, j = 0; i < m; ++i)
+    if (in[i]) { s2[j] = src[i]; d2[j] = dst[i]; ++j; }
+  adj_t g;
+  int rc = adj_build(n, ms, s2, d2, &g);
+  if (rc) { free(s2); free(d2); return rc; }
+  int64_t *tri = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  if (!tri) { free(s2); free(d2); adj_free(&g); return -OR_NOMEM; }
+  for (int64_t i = 0; i < ms; ++i) {
+    int32_t u = s2[i], v = d2[i];
+    int64_t a = g.off[u], ae = g.off[u + 1], b = g.off[v], be = g.off[v + 1], c = 0;
+    while (a < ae && b < be) {
+      if (g.nbr[a] < g.nbr[b]) ++a;
+      else if (g.nbr[a] > g.nbr[b]) ++b;
+      else { ++c; ++a; ++b; }
+    }
+    tri[u] += c;  /* each triangle at u is seen from both of its edges at u */
+    tri[v] += c;
+  }
+  int64_t nv = 0;
+  double cc = 0.0;
+  for (int32_t v = 0; v < n; ++v) {
+    int64_t d = g.off[v + 1] - g.off[v];
+    if (d == 0) continue;
+    ++nv;
+    if (d >= 2) cc += (double)(tri[v] / 2) / ((double)d * (double)(d - 1) / 2.0);
+  }
+  out[0] = (double)nv;
+  out[1] = (double)ms;
+  out[2] = nv ? cc / (double)nv : 0.0;
+  free(tri); free(s2); free(d2);
+  adj_free(&g);
+  return OR_OK;
+}
+
+/* Table 6's columns for T = the k_max-truss (edges with phi = k_max) and C =
+ * the c_max-core (edges with both ends of core number c_max):
+ * out = {V_T, E_T, k_max, CC_T, V_C, E_C, c_max, CC_C}. */
+int oracle_cohesion(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *phi,
+                    const int32_t *core, double *out) {
+  int32_t kmax = 0, cmax = 0;
+  for (int64_t i = 0; i < m; ++i) if (phi[i] > kmax) kmax = phi[i];
+  for (int32_t v = 0; v < n; ++v) if (core[v] > cmax) cmax = core[v];
+  uint8_t *in = (uint8_t *)calloc((size_t)m + 1, 1);
+  if (!in) return -OR_NOMEM;
+  double st[3];
+  for (int64_t i = 0; i < m; ++i) in[i] = (uint8_t)(phi[i] == kmax);
+  int rc = subgraph_stats(n, m, src, dst, in, st);
+  if (!rc) { out[0] = st[0]; out[1] = st[1]; out[2] = kmax; out[3] = st[2]; }
+  for (int64_t i = 0; !rc && i < m; ++i) in[i] = (uint8_t)(core[src[i]] == cmax && core[dst[i]] == cmax);
+  if (!rc) rc = subgraph_stats(n, m, src, dst, in, st);
+  if (!rc) { out[4] = st[0]; out[5] = st[1]; out[6] = cmax; out[7] = st[2]; }
+  free(in);
+  return rc;
+}

@@ -15,6 +15,8 @@ They share no code with the oracle or with the GPU library:
   x_brute / psi_brute    Procedure 6 by its words: for each end vertex, try
                          every x and count the other incident edges with
                          support >= x
+  clustering_brute       mean local clustering coefficient of an edge set
+                         (pairs of neighbours that are adjacent, per vertex)
 """
 from __future__ import annotations
 
@@ -140,3 +142,18 @@ def psi_brute(n, edges, sup):
     """psi(e) = min{sup(e), x_u, x_v} + 2 for every edge (Procedure 6, Step 6)."""
     return np.array([min(sup[i], x_brute(n, edges, sup, i, u), x_brute(n, edges, sup, i, v)) + 2
                      for i, (u, v) in enumerate(edges)], dtype=np.int64)
+
+
+def clustering_brute(n, edges):
+    """(vertices touching an edge, edges, mean over those vertices of
+    adjacent-neighbour pairs / all neighbour pairs; 0 for degree < 2)."""
+    nb = adjacency(n, edges)
+    vs = [v for v in range(n) if nb[v]]
+    total = 0.0
+    for v in vs:
+        d = len(nb[v])
+        if d < 2:
+            continue
+        links = sum(1 for a, b in itertools.combinations(sorted(nb[v]), 2) if b in nb[a])
+        total += links / (d * (d - 1) / 2)
+    return len(vs), len(set(canon(edges))), (total / len(vs) if vs else 0.0)

@@ -113,6 +113,66 @@ def test_upper_bound_closed_forms():
     assert (oracle.upper_bound(40, s, d) == 2).all()
 
 
+def test_core_numbers_brute_and_closed_forms():
+    """Core numbers by the bucket method equal repeated min-degree deletion;
+    K_k: k-1; cycles: 2; stars and paths: 1; and every k-truss lies in the
+    (k-1)-core (phi(e) - 1 <= core of both ends)."""
+    rng = np.random.default_rng(23)
+    for trial in range(150):
+        n = int(rng.integers(2, 40))
+        edges = brute.random_graph(rng, n, float(rng.uniform(0.05, 0.7)))
+        if not edges:
+            continue
+        s, d = _edges(edges)
+        core, cmax = oracle.core_numbers(n, s, d)
+        ref = brute.kcore_numbers(n, edges)
+        np.testing.assert_array_equal(core, ref)
+        assert cmax == ref.max()
+        phi, _ = oracle.truss(n, s, d)
+        assert (phi - 1 <= np.minimum(core[s], core[d])).all()
+    k = 9
+    s, d = _edges(list(itertools.combinations(range(k), 2)))
+    assert (oracle.core_numbers(k, s, d)[0] == k - 1).all()
+    s, d = _edges([(v, (v + 1) % 30) for v in range(30)])
+    assert (oracle.core_numbers(30, s, d)[0] == 2).all()
+    s, d = _edges([(0, v) for v in range(1, 30)] + [(30 + v, 31 + v) for v in range(20)])
+    assert (oracle.core_numbers(51, s, d)[0] == 1).all()
+
+
+def test_cohesion_statistics():
+    """Table 6's columns: K_k gives V = k, E = k(k-1)/2, k_max = k, c_max = k-1
+    and clustering 1 for both; a cycle has clustering 0; random graphs agree
+    with a brute-force count of adjacent neighbour pairs; on the Example 2
+    graph the 5-truss and the 4-core are both the K_5 on {a,b,c,d,e}."""
+    k = 7
+    s, d = _edges(list(itertools.combinations(range(k), 2)))
+    st = oracle.cohesion(k, s, d)
+    assert st == {"V_T": k, "E_T": k * (k - 1) // 2, "kmax": k, "CC_T": 1.0,
+                  "V_C": k, "E_C": k * (k - 1) // 2, "cmax": k - 1, "CC_C": 1.0}
+    s, d = _edges([(v, (v + 1) % 12) for v in range(12)])
+    st = oracle.cohesion(12, s, d)
+    assert st["CC_T"] == 0.0 and st["E_T"] == 12 and st["kmax"] == 2
+    n, s, d, _ = golden_io.fig2()
+    st = oracle.cohesion(n, s, d)
+    assert (st["V_T"], st["E_T"], st["kmax"], st["V_C"], st["E_C"], st["cmax"]) == (5, 10, 5, 5, 10, 4)
+    rng = np.random.default_rng(29)
+    for trial in range(40):
+        n = int(rng.integers(5, 35))
+        edges = brute.random_graph(rng, n, float(rng.uniform(0.15, 0.8)))
+        if not edges:
+            continue
+        s, d = _edges(edges)
+        phi, kmax = oracle.truss(n, s, d)
+        core, cmax = oracle.core_numbers(n, s, d)
+        st = oracle.cohesion(n, s, d, phi, core)
+        T = [e for e, p in zip(edges, phi) if p == kmax]
+        C = [(u, v) for u, v in edges if core[u] == cmax and core[v] == cmax]
+        vt, et, cct = brute.clustering_brute(n, T)
+        vc, ec, ccc = brute.clustering_brute(n, C)
+        assert (st["V_T"], st["E_T"], st["V_C"], st["E_C"]) == (vt, et, vc, ec)
+        assert abs(st["CC_T"] - cct) < 1e-12 and abs(st["CC_C"] - ccc) < 1e-12
+
+
 # ---------------------------------------------------------------- closed forms
 
 @pytest.mark.parametrize("k", [3, 4, 5, 8, 13])
