@@ -230,6 +230,41 @@ int truss_topdown_workspace_size(const truss_graph *g, const truss_options *opts
 int truss_topdown(const truss_graph *g, int32_t t, int32_t *truss_out, int32_t *kmin_out, int32_t *kmax_out,
                   const truss_options *opts, truss_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- k-cores and the cohesion comparison of Section 7 (Table 6) ---------- */
+/* Core numbers: the c-core is the largest subgraph whose vertices all have
+ * degree >= c; core(v) is the largest c whose c-core holds v (0 for isolated
+ * vertices).  core_out (device) int32[n], indexed by vertex id in both
+ * formats; *cmax_out (host, nullable) = max core(v).  The graph is validated
+ * as for truss_decompose.  Workspace from truss_core_workspace_size; the
+ * call synchronises the stream (the host steps the peeling levels). */
+int truss_core_workspace_size(const truss_graph *g, size_t *bytes);
+int truss_core_numbers(const truss_graph *g, int32_t *core_out, int32_t *cmax_out, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* Table 6's columns for T = the k_max-truss (the edges with phi(e) = k_max;
+ * k_max is the largest truss number) and C = the c_max-core (the edges whose
+ * two ends have core number c_max): vertex and edge counts, k_max and c_max,
+ * and the mean local clustering coefficient over the subgraph's vertices,
+ * where a vertex of degree d >= 2 in the subgraph with t triangles there has
+ * coefficient t / (d (d - 1) / 2) and a vertex of degree 1 has 0.  Counts are
+ * exact; the means are fp64 sums taken in a tree order (their last bits can
+ * differ from a sequential sum). */
+typedef struct truss_cohesion_stats {
+  int64_t v_t, e_t;  /* |V_T|, |E_T|                                */
+  int32_t kmax, pad0;
+  double cc_t;       /* mean clustering coefficient of T            */
+  int64_t v_c, e_c;  /* |V_C|, |E_C|                                */
+  int32_t cmax, pad1;
+  double cc_c;       /* mean clustering coefficient of C            */
+} truss_cohesion_stats;
+
+/* Runs the truss decomposition (opts as for truss_decompose, nullable), the
+ * core numbers and the support of T and of C inside themselves.  out (host)
+ * receives the statistics.  Synchronises the stream. */
+int truss_cohesion_workspace_size(const truss_graph *g, size_t *bytes);
+int truss_cohesion(const truss_graph *g, const truss_options *opts, truss_cohesion_stats *out, void *ws,
+                   size_t ws_bytes, void *stream);
+
 /* ---- tracing: the per-decision record behind the learned scheduler ----- */
 /* Peeling level actions: bit 0 = probe (0 hash table, 1 binary search),
  * bit 1 = frontier mode (0 sparse worklist, 1 dense re-scan). */

@@ -83,6 +83,17 @@ class Trace(ctypes.Structure):
                 ("sup_ms", ctypes.c_float * SCHED_SUP_BINS)]
 
 
+class CohesionStats(ctypes.Structure):
+    _fields_ = [("v_t", ctypes.c_int64), ("e_t", ctypes.c_int64), ("kmax", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("cc_t", ctypes.c_double),
+                ("v_c", ctypes.c_int64), ("e_c", ctypes.c_int64), ("cmax", ctypes.c_int32),
+                ("pad1", ctypes.c_int32), ("cc_c", ctypes.c_double)]
+
+    def to_dict(self):
+        return {"V_T": self.v_t, "E_T": self.e_t, "kmax": self.kmax, "CC_T": self.cc_t,
+                "V_C": self.v_c, "E_C": self.e_c, "cmax": self.cmax, "CC_C": self.cc_c}
+
+
 _lib = None
 
 
@@ -124,6 +135,10 @@ def load_library():
     lib.truss_topdown_workspace_size.argtypes = [gp, op, szp]
     lib.truss_topdown.argtypes = [gp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), op, sp, vp,
                                   ctypes.c_size_t, vp]
+    lib.truss_core_workspace_size.argtypes = [gp, szp]
+    lib.truss_core_numbers.argtypes = [gp, vp, ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
+    lib.truss_cohesion_workspace_size.argtypes = [gp, szp]
+    lib.truss_cohesion.argtypes = [gp, op, ctypes.POINTER(CohesionStats), vp, ctypes.c_size_t, vp]
     lib.truss_mlp_param_count.argtypes = [i32, i32, i32]
     lib.truss_mlp_workspace_size.argtypes = [i32, i32, i32, i32, szp]
     lib.truss_mlp_forward.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, ctypes.c_size_t, vp]
@@ -138,6 +153,8 @@ def load_library():
               "truss_batch_workspace_size", "truss_batch", "truss_version", "truss_decompose_traced",
               "truss_batch_plan_create", "truss_batch_plan_run", "truss_batch_autotune",
               "truss_upper_bound", "truss_topdown_workspace_size", "truss_topdown",
+              "truss_core_workspace_size", "truss_core_numbers", "truss_cohesion_workspace_size",
+              "truss_cohesion",
               "truss_mlp_param_count", "truss_mlp_workspace_size", "truss_mlp_forward",
               "truss_mlp_backward", "truss_mlp_train", "truss_sched_part_floats",
               "truss_sched_model_floats", "truss_sched_train_workspace_size", "truss_sched_train"):
@@ -509,3 +526,37 @@ def truss_topdown(graph: Graph, t: int, opts: Options | None = None, out=None, w
                              ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
                              _stream(stream)))
     return out, kmin.value, kmax.value, st.to_dict()
+
+
+def truss_core_numbers(graph: Graph, out=None, ws=None, stream=None):
+    """(core numbers of every vertex as int32[n], c_max): the c-core is the
+    largest subgraph with minimum degree >= c (the k-core of Section 7)."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(max(graph.n, 1), dtype=torch.int32, device=graph.device)
+    g = graph._c()
+    if ws is None:
+        b = ctypes.c_size_t(0)
+        _check(lib.truss_core_workspace_size(ctypes.byref(g), ctypes.byref(b)))
+        ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
+    cmax = ctypes.c_int32(0)
+    _check(lib.truss_core_numbers(ctypes.byref(g), _ptr(out), ctypes.byref(cmax), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return out[:graph.n], cmax.value
+
+
+def truss_cohesion(graph: Graph, opts: Options | None = None, ws=None, stream=None):
+    """Table 6's columns for the k_max-truss and the c_max-core: dict with
+    V_T, E_T, kmax, CC_T, V_C, E_C, cmax, CC_C."""
+    torch = _torch()
+    lib = load_library()
+    g = graph._c()
+    if ws is None:
+        b = ctypes.c_size_t(0)
+        _check(lib.truss_cohesion_workspace_size(ctypes.byref(g), ctypes.byref(b)))
+        ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
+    st = CohesionStats()
+    _check(lib.truss_cohesion(ctypes.byref(g), ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
+                              ws.numel(), _stream(stream)))
+    return st.to_dict()

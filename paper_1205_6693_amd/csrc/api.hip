@@ -551,6 +551,215 @@ int run_topdown(const truss_graph* g, int32_t t, int32_t* out, int32_t* kmin_out
   return TRUSS_OK;
 }
 
+// ---- core numbers and the cohesion statistics of Table 6 ---------------------------
+size_t core_layout(const truss_graph* g, Arena& a) {
+  a.take<int>(64);
+  build_workspace(g, a);
+  core_workspace(g->n, a);
+  return a.used;
+}
+
+int run_core(const truss_graph* g, int32_t* core_out, int32_t* cmax_out, void* ws, size_t ws_bytes, hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (g->n > 0 && !core_out) { set_last_error("core_out is NULL"); return TRUSS_E_INVAL; }
+  Arena need;
+  need.counting = true;
+  const size_t bytes = core_layout(g, need);
+  if (!ws || ws_bytes < bytes) {
+    set_last_error("workspace of %zu bytes given, %zu needed", ws_bytes, bytes);
+    return TRUSS_E_WORKSPACE;
+  }
+  if (cmax_out) *cmax_out = 0;
+  Arena a;
+  a.base = static_cast<char*>(ws);
+  a.cap = ws_bytes;
+  int* d_err = a.take<int>(64);
+  DevGraph dg;
+  rc = build_graph(g, a, dg, d_err, s);
+  if (rc) return rc;
+  int32_t cmax = 0;
+  rc = compute_core_numbers(dg, core_out, &cmax, a, s);
+  if (rc) return rc;
+  if (cmax_out) *cmax_out = cmax;
+  return TRUSS_OK;
+}
+
+// canonical edges whose truss number (given in the caller's indexing) is k
+__global__ void k_select_truss(const int32_t* __restrict__ phi, const int32_t* __restrict__ perm,
+                               const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m, int k,
+                               int32_t* __restrict__ ssrc, int32_t* __restrict__ sdst, int* __restrict__ count) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool take = e < m && phi[perm ? perm[e] : e] == k;
+  const int pos = wave_append(count, take);
+  if (take) {
+    ssrc[pos] = eu[e];
+    sdst[pos] = ev[e];
+  }
+}
+
+// canonical edges with both ends of core number c
+__global__ void k_select_core(const int32_t* __restrict__ core, const int32_t* __restrict__ eu,
+                              const int32_t* __restrict__ ev, int64_t m, int c, int32_t* __restrict__ ssrc,
+                              int32_t* __restrict__ sdst, int* __restrict__ count) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  bool take = false;
+  int32_t u = 0, v = 0;
+  if (e < m) {
+    u = eu[e];
+    v = ev[e];
+    take = core[u] == c && core[v] == c;
+  }
+  const int pos = wave_append(count, take);
+  if (take) {
+    ssrc[pos] = u;
+    sdst[pos] = v;
+  }
+}
+
+struct CohesionBufs {
+  int* d_count;
+  int32_t *phi, *core, *tsrc, *tdst, *csrc, *cdst, *ssup;
+  char* stats_ws;
+  size_t stats_bytes;
+  char* region;  // decomposition, then build + core numbers, then subgraph support
+  size_t region_bytes;
+};
+
+// the edge-list graph of up to m edges over n vertices (workspace sizes only)
+truss_graph edge_list_shape(int32_t n, int64_t m) {
+  truss_graph sg;
+  memset(&sg, 0, sizeof(sg));
+  sg.fmt = TRUSS_FMT_EDGES;
+  sg.n = n;
+  sg.m = m;
+  sg.src = sg.dst = reinterpret_cast<const int32_t*>(1);
+  return sg;
+}
+
+size_t cohesion_layout(const truss_graph* g, Arena& a, CohesionBufs* out) {
+  CohesionBufs b;
+  const size_t m1 = (size_t)g->m + 1, n1 = (size_t)g->n + 1;
+  b.d_count = a.take<int>(64);
+  b.phi = a.take<int32_t>(m1);
+  b.core = a.take<int32_t>(n1);
+  b.tsrc = a.take<int32_t>(m1);
+  b.tdst = a.take<int32_t>(m1);
+  b.csrc = a.take<int32_t>(m1);
+  b.cdst = a.take<int32_t>(m1);
+  b.ssup = a.take<int32_t>(m1);
+  {
+    Arena sa;
+    sa.counting = true;
+    sa.take<int32_t>(n1);
+    sa.take<unsigned long long>(n1);
+    sa.take<double>(n1);
+    sa.take<double>(4);
+    b.stats_bytes = sa.used;
+  }
+  b.stats_ws = a.take<char>(b.stats_bytes);
+  size_t r = 0;
+  {
+    Arena x;
+    x.counting = true;
+    Plan p;
+    layout(g, x, p, nullptr);
+    r = x.used;
+  }
+  {
+    Arena x;
+    x.counting = true;
+    const size_t c = core_layout(g, x);
+    r = c > r ? c : r;
+  }
+  {
+    const truss_graph sg = edge_list_shape(g->n, g->m);
+    Arena x;
+    x.counting = true;
+    Plan p;
+    layout(&sg, x, p, nullptr);
+    r = x.used > r ? x.used : r;
+  }
+  b.region_bytes = r;
+  b.region = a.take<char>(r);
+  if (out) *out = b;
+  return a.used;
+}
+
+int subgraph_cohesion(const truss_graph* g, const CohesionBufs& b, const int32_t* src, const int32_t* dst,
+                      int64_t cnt, int64_t* nv, double* cc, hipStream_t s) {
+  truss_graph sg;
+  memset(&sg, 0, sizeof(sg));
+  sg.fmt = TRUSS_FMT_EDGES;
+  sg.n = g->n;
+  sg.m = cnt;
+  sg.src = src;
+  sg.dst = dst;
+  int rc = run_single(&sg, kModeSupport, b.ssup, nullptr, nullptr, nullptr, b.region, b.region_bytes, s, nullptr);
+  if (rc) return rc;
+  Arena sa;
+  sa.base = b.stats_ws;
+  sa.cap = b.stats_bytes;
+  double v = 0.0;
+  rc = subgraph_vertex_stats(g->n, src, dst, b.ssup, cnt, sa, &v, cc, s);
+  *nv = (int64_t)v;
+  return rc;
+}
+
+int run_cohesion(const truss_graph* g, const truss_options* opts, truss_cohesion_stats* out, void* ws,
+                 size_t ws_bytes, hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if ((rc = validate_options(opts))) return rc;
+  if (!out) { set_last_error("out is NULL"); return TRUSS_E_INVAL; }
+  Arena need;
+  need.counting = true;
+  const size_t bytes = cohesion_layout(g, need, nullptr);
+  if (!ws || ws_bytes < bytes) {
+    set_last_error("workspace of %zu bytes given, %zu needed", ws_bytes, bytes);
+    return TRUSS_E_WORKSPACE;
+  }
+  memset(out, 0, sizeof(*out));
+  Arena a;
+  a.base = static_cast<char*>(ws);
+  a.cap = ws_bytes;
+  CohesionBufs b;
+  cohesion_layout(g, a, &b);
+  // truss numbers (k_max from the stats)
+  truss_stats st;
+  rc = run_single(g, kModeDecompose, b.phi, nullptr, opts, &st, b.region, b.region_bytes, s, nullptr);
+  if (rc) return rc;
+  const int kmax = g->m > 0 ? st.kmax : 0;
+  // core numbers; the graph built for them also lists the canonical edges
+  Arena r;
+  r.base = b.region;
+  r.cap = b.region_bytes;
+  int* d_err = r.take<int>(64);
+  DevGraph dg;
+  if ((rc = build_graph(g, r, dg, d_err, s))) return rc;
+  int32_t cmax = 0;
+  if ((rc = compute_core_numbers(dg, b.core, &cmax, r, s))) return rc;
+  int cnt[2] = {0, 0};
+  if (g->m > 0) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, b.d_count, (int64_t)64, 0);
+    hipLaunchKernelGGL(k_select_truss, dim3(grid_for(g->m)), dim3(kT), 0, s, b.phi, dg.perm, dg.eu, dg.ev, g->m, kmax,
+                       b.tsrc, b.tdst, b.d_count);
+    hipLaunchKernelGGL(k_select_core, dim3(grid_for(g->m)), dim3(kT), 0, s, b.core, dg.eu, dg.ev, g->m, cmax, b.csrc,
+                       b.cdst, b.d_count + 1);
+    TRUSS_HIP(hipGetLastError());
+    TRUSS_HIP(hipMemcpyAsync(cnt, b.d_count, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    TRUSS_HIP(hipStreamSynchronize(s));
+  }
+  // the region is reused below: the graph built above is no longer needed
+  out->kmax = kmax;
+  out->cmax = cmax;
+  out->e_t = cnt[0];
+  out->e_c = cnt[1];
+  if ((rc = subgraph_cohesion(g, b, b.tsrc, b.tdst, cnt[0], &out->v_t, &out->cc_t, s))) return rc;
+  if ((rc = subgraph_cohesion(g, b, b.csrc, b.cdst, cnt[1], &out->v_c, &out->cc_c, s))) return rc;
+  return TRUSS_OK;
+}
+
 }  // namespace
 
 void set_last_error(const char* fmt, ...) {
@@ -638,6 +847,36 @@ int truss_topdown_workspace_size(const truss_graph* g, const truss_options* opts
 int truss_topdown(const truss_graph* g, int32_t t, int32_t* truss_out, int32_t* kmin_out, int32_t* kmax_out,
                   const truss_options* opts, truss_stats* stats, void* ws, size_t ws_bytes, void* stream) {
   return run_topdown(g, t, truss_out, kmin_out, kmax_out, opts, stats, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int truss_core_workspace_size(const truss_graph* g, size_t* bytes) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (!bytes) { set_last_error("bytes is NULL"); return TRUSS_E_INVAL; }
+  Arena a;
+  a.counting = true;
+  *bytes = core_layout(g, a);
+  return TRUSS_OK;
+}
+
+int truss_core_numbers(const truss_graph* g, int32_t* core_out, int32_t* cmax_out, void* ws, size_t ws_bytes,
+                       void* stream) {
+  return run_core(g, core_out, cmax_out, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int truss_cohesion_workspace_size(const truss_graph* g, size_t* bytes) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (!bytes) { set_last_error("bytes is NULL"); return TRUSS_E_INVAL; }
+  Arena a;
+  a.counting = true;
+  *bytes = cohesion_layout(g, a, nullptr);
+  return TRUSS_OK;
+}
+
+int truss_cohesion(const truss_graph* g, const truss_options* opts, truss_cohesion_stats* out, void* ws,
+                   size_t ws_bytes, void* stream) {
+  return run_cohesion(g, opts, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
 const char* truss_strerror(int code) {

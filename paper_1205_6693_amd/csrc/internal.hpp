@@ -113,6 +113,16 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
 void compute_upper_bound(const DevGraph& dg, const int2* sr, int32_t* h, int32_t* ch, int32_t* psi, int32_t* hs,
                          hipStream_t s);
 
+// Core numbers of every vertex (k-cores); syncs the stream once per peeling
+// step.  core: n entries.  Workspace: core_workspace(n) after the build's.
+size_t core_workspace(int32_t n, Arena& a);
+int compute_core_numbers(const DevGraph& dg, int32_t* core, int32_t* cmax_out, Arena& a, hipStream_t s);
+// Vertices of degree > 0 in the subgraph given by ms edges (su, sv) and
+// their mean local clustering coefficient; sup[i] = triangles of edge i in the
+// subgraph.  Syncs the stream.
+int subgraph_vertex_stats(int32_t n, const int32_t* su, const int32_t* sv, const int32_t* sup, int64_t ms, Arena& a,
+                          double* nv_out, double* cc_out, hipStream_t s);
+
 void set_last_error(const char* fmt, ...);
 int validate_options(const truss_options* o);  // TRUSS_OK or TRUSS_E_INVAL (message set)
 int device_grid_blocks(const void* kernel, int block, size_t lds);

@@ -2,9 +2,11 @@
 
 Calls only the CPU oracle (oracle/) on seeded synthetic inputs (graphgen/), never
 the GPU library.  Each output file records, for one workload, the oracle's
-truss numbers and supports in canonical edge order (u < v, sorted by (u, v),
-which is also the library's CSR output order) as SHA-256 digests of the int32
-arrays, the triangle count, k_max and the size of every k-class.
+truss numbers, supports and upper bounds in canonical edge order (u < v, sorted
+by (u, v), which is also the library's CSR output order) and the core numbers
+by vertex as SHA-256 digests of the int32 arrays, the triangle count, k_max,
+c_max, the size of every k-class and the cohesion statistics of the k_max-truss
+and the c_max-core (Table 6's columns).
 
 Usage: python tests/golden/make_golden.py rmat20      (about 5 minutes, one core)
        python tests/golden/make_golden.py chunglu4m   (the 57M-edge Chung-Lu graph; about 8 minutes)
@@ -81,10 +83,13 @@ def main(name):
     sup, tri = oracle.support_fwd(n, s, d)
     phi, kmax = oracle.truss(n, s, d)
     psi = oracle.upper_bound(n, s, d, sup)
+    core, cmax = oracle.core_numbers(n, s, d)
+    coh = oracle.cohesion(n, s, d, phi=phi, core=core)
     hist = np.bincount(phi, minlength=kmax + 1)
     lines = [
         "# Oracle results for workload %s (seed 1), canonical edge order." % name,
-        "# Written by tests/golden/make_golden.py from oracle.support_fwd, oracle.truss and oracle.upper_bound",
+        "# Written by tests/golden/make_golden.py from oracle.support_fwd, oracle.truss, oracle.upper_bound,",
+        "# oracle.core_numbers and oracle.cohesion",
         "# (%.0f s on one core)." % (time.time() - t0),
         "n: %d" % n,
         "m: %d" % s.size,
@@ -93,6 +98,9 @@ def main(name):
         "truss_sha256: %s" % digest(phi),
         "support_sha256: %s" % digest(sup),
         "psi_sha256: %s" % digest(psi),
+        "core_sha256: %s" % digest(core),
+        "cmax: %d" % cmax,
+        "cohesion: %s" % " ".join("%s=%r" % (k, v) for k, v in coh.items()),
         "class_sizes: %s" % " ".join("%d:%d" % (k, c) for k, c in enumerate(hist) if c),
     ]
     path = os.path.join(HERE, "oracle_%s.txt" % name)

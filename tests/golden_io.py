@@ -61,8 +61,11 @@ def oracle_record(name):
                 continue
             key, val = line.split(":", 1)
             val = val.strip()
-            if key in ("n", "m", "triangles", "kmax", "graphs"):
+            if key in ("n", "m", "triangles", "kmax", "graphs", "cmax"):
                 rec[key] = int(val)
+            elif key == "cohesion":
+                rec[key] = {a: (float(b) if a.startswith("CC") else int(b))
+                            for a, b in (t.split("=") for t in val.split())}
             elif key in ("graph_kmax", "graph_m"):
                 rec[key] = [int(t) for t in val.split()]
             elif key == "class_sizes":

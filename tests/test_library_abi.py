@@ -148,3 +148,24 @@ def test_trace_layout_and_network_sizes(T):
     tr.level_cap = 4
     assert lib.truss_decompose_traced(ctypes.byref(g), p, None, None, ctypes.byref(tr), None, 0,
                                       None) == T.E_WORKSPACE
+
+
+def test_core_and_cohesion_sizes_and_errors(T):
+    lib = T.load_library()
+    assert ctypes.sizeof(T.CohesionStats) == 64
+    b = ctypes.c_size_t(0)
+    assert lib.truss_core_workspace_size(ctypes.byref(_graph(T, 1000, 5000)), ctypes.byref(b)) == 0
+    core_bytes = b.value
+    assert core_bytes >= 1000 * 12
+    assert lib.truss_cohesion_workspace_size(ctypes.byref(_graph(T, 1000, 5000)), ctypes.byref(b)) == 0
+    assert b.value > core_bytes
+    assert lib.truss_core_workspace_size(None, ctypes.byref(b)) == T.E_INVAL
+    assert lib.truss_cohesion_workspace_size(ctypes.byref(_graph(T, -1, 5)), ctypes.byref(b)) == T.E_INVAL
+    # too small a workspace and missing outputs fail before any device call
+    g = _graph(T, 1000, 5000)
+    cmax = ctypes.c_int32(0)
+    assert lib.truss_core_numbers(ctypes.byref(g), None, ctypes.byref(cmax), None, 0, None) == T.E_INVAL
+    assert lib.truss_core_numbers(ctypes.byref(g), 4096, ctypes.byref(cmax), 4096, 16, None) == T.E_WORKSPACE
+    st = T.CohesionStats()
+    assert lib.truss_cohesion(ctypes.byref(g), None, None, 4096, 1 << 40, None) == T.E_INVAL
+    assert lib.truss_cohesion(ctypes.byref(g), None, ctypes.byref(st), 4096, 16, None) == T.E_WORKSPACE
