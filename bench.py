@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other scheduler forms")
     ap.add_argument("--topdown", type=int, default=0, metavar="T",
                     help="also time the top-T k-classes (upper bound + top-down) against the full decomposition")
+    ap.add_argument("--cohesion", action="store_true",
+                    help="also time the core numbers and the cohesion statistics of Table 6")
     ap.add_argument("--batch-shape", type=int, nargs=2, default=None, metavar=("THREADS", "ILP"),
                     help="batch4096: use this shape instead of the autotuner's")
     ap.add_argument("--probe", default="auto", choices=["auto", "hash", "bsearch"])
@@ -422,10 +424,36 @@ def main():
                              "full_over_topdown": ms_per_step / td_ms, "upper_bound_ms": ub_ms}
         print("top-%d classes: %.2f ms (k %d..%d, last subgraph %d edges, %d decompositions)"
               % (args.topdown, td_ms, kmin, kmax, tst["m"], tst["launches"]), file=sys.stderr, flush=True)
+    if args.cohesion:
+        result["cohesion"] = time_cohesion(T, torch, g, opts, args)
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale, args.seed)
     print(json.dumps(result), flush=True)
+
+
+def time_cohesion(T, torch, g, opts, args):
+    """Core numbers and Table 6's statistics (both include their own build;
+    the statistics include a full decomposition, the core numbers and the
+    support of the two subgraphs)."""
+    reps = max(1, min(args.steps, 3))
+    core, cmax = T.truss_core_numbers(g)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        core, cmax = T.truss_core_numbers(g)
+    torch.cuda.synchronize()
+    core_ms = (time.perf_counter() - t1) * 1e3 / reps
+    st = T.truss_cohesion(g, opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        st = T.truss_cohesion(g, opts)
+    torch.cuda.synchronize()
+    coh_ms = (time.perf_counter() - t1) * 1e3 / reps
+    print("core numbers %.2f ms (c_max %d); cohesion statistics %.2f ms: %s" % (core_ms, cmax, coh_ms, st),
+          file=sys.stderr, flush=True)
+    return dict(st, core_ms=core_ms, cohesion_ms=coh_ms)
 
 
 if __name__ == "__main__":

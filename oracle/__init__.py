@@ -13,6 +13,9 @@ Functions follow Wang & Cheng, "Truss Decomposition in Massive Networks":
   top_classes                    -- the top-t k-classes of Algorithm 7 from phi
   core_numbers                   -- core number of every vertex (Section 7)
   cohesion                       -- Table 6's statistics of the k_max-truss and c_max-core
+  lower_bounding                 -- Algorithm 3: per-edge lower bounds and Phi_2 over
+                                    neighbourhood-subgraph partitions (Lemma 1)
+  bottom_up                      -- Algorithm 4 with Procedures 5 and 9 on those bounds
   csr_to_edges                   -- canonical upper-CSR edge order
 """
 from __future__ import annotations
@@ -28,7 +31,7 @@ _SRC = os.path.join(_HERE, "truss_oracle.c")
 _LIB = os.path.join(_HERE, "_truss_oracle.so")
 
 # error-code magnitudes (negative on return)
-INVAL, TOOBIG, ROWPTR, RANGE, SELFLOOP, UNSORTED, DUP, ASYM, NOMEM = range(1, 10)
+INVAL, TOOBIG, ROWPTR, RANGE, SELFLOOP, UNSORTED, DUP, ASYM, NOMEM, CAP, STALL = range(1, 12)
 
 _lib = None
 
@@ -62,6 +65,11 @@ def _load():
         lib.oracle_core_numbers.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, c_i32p]
         lib.oracle_cohesion.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, i32p,
                                         np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")]
+        u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+        lib.oracle_lower_bounding.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, ctypes.c_void_p,
+                                              ctypes.c_int64, i32p, u8p, i64p]
+        lib.oracle_bottom_up.argtypes = [ctypes.c_int32, ctypes.c_int64, i32p, i32p, i32p, u8p, ctypes.c_int32,
+                                         ctypes.c_int64, i32p, i64p]
         for f in (lib.oracle_validate_edges, lib.oracle_validate_csr, lib.oracle_csr_to_edges,
                   lib.oracle_support_def, lib.oracle_support_fwd, lib.oracle_truss):
             f.restype = ctypes.c_int
@@ -201,3 +209,49 @@ def cohesion(n: int, src, dst, phi=None, core=None):
         raise OracleError(rc)
     keys = ["V_T", "E_T", "kmax", "CC_T", "V_C", "E_C", "cmax", "CC_C"]
     return {k: (float(v) if k.startswith("CC") else int(v)) for k, v in zip(keys, out)}
+
+
+def lower_bounding(n: int, src, dst, cap: int, first_part=None):
+    """Algorithm 3: (lb[m], phi2[m] as bool, info) where lb is the lower bound
+    of every edge and phi2 marks the edges output as Phi_2.  cap = most edges
+    a neighbourhood subgraph may hold; first_part (optional) = part id of every
+    vertex for the first pass (later passes use the sequential partition)."""
+    src, dst = _edges(src, dst)
+    rc = _load().oracle_validate_edges(n, src.size, src, dst)
+    if rc:
+        raise OracleError(rc)
+    m = src.size
+    lb = np.zeros(max(m, 1), dtype=np.int32)
+    phi2 = np.zeros(max(m, 1), dtype=np.uint8)
+    info = np.zeros(5, dtype=np.int64)
+    fp = None
+    if first_part is not None:
+        fp = np.ascontiguousarray(first_part, dtype=np.int32)
+        if fp.shape != (n,):
+            raise ValueError("first_part must hold one part id per vertex")
+    rc = _load().oracle_lower_bounding(n, m, src, dst, None if fp is None else fp.ctypes.data_as(ctypes.c_void_p),
+                                       int(cap), lb, phi2, info)
+    if rc:
+        raise OracleError(rc)
+    keys = ["passes", "subgraphs", "phi2_edges", "gnew_edges", "max_subgraph"]
+    return lb[:m], phi2[:m].astype(bool), dict(zip(keys, map(int, info)))
+
+
+def bottom_up(n: int, src, dst, cap: int, first_part=None):
+    """Bottom-up truss decomposition (Algorithm 3, then Algorithm 4 with
+    Procedure 5, or Procedure 9 when a candidate subgraph exceeds cap):
+    (phi[m], lb[m], info)."""
+    src, dst = _edges(src, dst)
+    lb, phi2, info = lower_bounding(n, src, dst, cap, first_part)
+    m = src.size
+    phi = np.zeros(max(m, 1), dtype=np.int32)
+    binfo = np.zeros(5, dtype=np.int64)
+    kstart = 3 if info["passes"] <= 1 else 2
+    rc = _load().oracle_bottom_up(n, m, src, dst, np.ascontiguousarray(lb, dtype=np.int32),
+                                  np.ascontiguousarray(phi2, dtype=np.uint8), kstart, int(cap), phi, binfo)
+    if rc:
+        raise OracleError(rc)
+    keys = ["candidates", "proc9_calls", "proc9_scans", "max_candidate", "kmax"]
+    info.update(zip(keys, map(int, binfo)))
+    info["kstart"] = kstart
+    return phi[:m], lb, info

@@ -566,3 +566,345 @@ int oracle_cohesion(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
   free(in);
   return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Bottom-up truss decomposition (Section 5): LowerBounding (Algorithm 3),    */
+/* then Algorithm 4 with Procedure 5, or Procedure 9 (Appendix) when the      */
+/* candidate subgraph exceeds the memory budget.                              */
+/* ------------------------------------------------------------------------- */
+/* Readings (the paper leaves the partition open and is at odds with itself
+ * on the 2-class; the design notes list these):
+ *   - Memory budget: cap = the most edges a neighbourhood subgraph may hold.
+ *   - Partition of a vertex set (Step 3 of Algorithm 3, Step 4 of Procedure
+ *     9): parts grown breadth-first over the edges of the graph being
+ *     partitioned (the current G; H' in Procedure 9), each vertex weighted
+ *     by its degree in the graph the neighbourhood subgraphs are taken from
+ *     (the current G; the current H), a part's weight sum at most cap
+ *     (grow_partition below; a vertex alone above cap is an error).
+ *     |NS(P)| <= the weight sum, so every part fits.  A pass that leaves
+ *     every edge between parts stalls (an error: the budget is too small for
+ *     this graph).  The first pass of Algorithm 3 may use a partition given
+ *     by the caller (Example 3's {a,b,c,l}, {d,e,f,g}, {h,i,j,k}).
+ *   - The 2-class: an internal edge's support in the current graph is its
+ *     support in the input graph only in the first pass (later passes lack the
+ *     internal edges removed before), so only the first pass outputs internal
+ *     edges of support 0 as Phi_2; internal edges of later passes go to G_new
+ *     with their bound, and Algorithm 4 then starts from k = 2 instead of 3.
+ *     Example 3 likewise stops stage 1 after one pass.
+ *   - The bound starts at 2 (Example 3; Step 1 says 0): every edge lies in
+ *     some neighbourhood subgraph, where its local truss number is >= 2, so
+ *     the two starts give the same bounds.
+ *   - Algorithm 4 skips a k for which no edge of G_new has bound <= k: U_k
+ *     and hence Phi_k are empty there.  k starts at the smallest bound >= the
+ *     start value.
+ *   - Procedure 9: F = NS(P_i) is taken in the current H (so that supports of
+ *     its internal edges are exact); the edges eligible for Phi_k are those
+ *     internal to both F and H; P ranges over the vertices that still have an
+ *     edge of H' (not yet internal to an F in this scan), weighted by their
+ *     degree in H.  A scan without new Phi_k edges ends the procedure. */
+enum { OR_CAP = 10, OR_STALL = 11 };
+
+/* Parts grown breadth-first (Step 3 of Algorithm 3, Step 4 of Procedure 9).
+ * Vertices qualify when they have an edge with mask[e] set.  A part starts
+ * at the smallest-id qualifying vertex not yet placed and grows
+ * breadth-first: from each vertex it holds (in the order added) it takes
+ * every unplaced neighbour over such edges, by ascending id, whose weight
+ * still fits (weight sum <= cap); a neighbour that does not fit is left for
+ * a later part.  When the growth stops, the part goes on from the next
+ * unplaced qualifying vertex by id if that one still fits, else a new part
+ * starts there.  part[v] = part id, -1 for vertices that do not qualify.
+ * Returns the number of parts or a negative error. */
+static int64_t grow_partition(const adj_t *g, const uint8_t *mask, const int64_t *w, int64_t cap, int32_t *part,
+                              int32_t *queue) {
+  int64_t parts = 0, sum = 0;
+  for (int32_t v = 0; v < g->n; ++v) part[v] = -1;
+  for (int32_t r = 0; r < g->n; ++r) {
+    if (part[r] >= 0) continue;
+    int has = 0;
+    for (int64_t j = g->off[r]; j < g->off[r + 1] && !has; ++j) has = mask[g->eid[j]];
+    if (!has) continue;
+    if (w[r] > cap) return -OR_CAP;
+    if (parts == 0 || sum + w[r] > cap) { ++parts; sum = 0; }
+    const int32_t p = (int32_t)(parts - 1);
+    int32_t head = 0, tail = 0;
+    sum += w[r];
+    part[r] = p;
+    queue[tail++] = r;
+    while (head < tail) {
+      const int32_t v = queue[head++];
+      for (int64_t j = g->off[v]; j < g->off[v + 1]; ++j) {
+        const int32_t x = g->nbr[j];
+        if (!mask[g->eid[j]] || part[x] >= 0 || sum + w[x] > cap) continue;
+        part[x] = p;
+        sum += w[x];
+        queue[tail++] = x;
+      }
+    }
+  }
+  return parts;
+}
+
+/* Local truss numbers and supports of the subgraph given by the edge ids
+ * ids[0..h) (Algorithm 2 and Definition 1 on that subgraph). */
+static int local_truss(int32_t n, const int32_t *src, const int32_t *dst, const int64_t *ids, int64_t h,
+                       int32_t *phi_h, int32_t *sup_h) {
+  int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(h + 1));
+  int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)(h + 1));
+  if (!s || !d) { free(s); free(d); return -OR_NOMEM; }
+  for (int64_t i = 0; i < h; ++i) { s[i] = src[ids[i]]; d[i] = dst[ids[i]]; }
+  int rc = oracle_support_fwd(n, h, s, d, sup_h, NULL);
+  if (!rc && phi_h) rc = oracle_truss(n, h, s, d, phi_h, NULL);
+  free(s); free(d);
+  return rc;
+}
+
+/* LowerBounding (Algorithm 3).  lb[e] = the bound of every edge; phi2[e] = 1
+ * for the edges output as Phi_2.  info (nullable) = {passes, neighbourhood
+ * subgraphs, |Phi_2|, |G_new|, largest subgraph}. */
+int oracle_lower_bounding(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                          const int32_t *first_part, int64_t cap, int32_t *lb, uint8_t *phi2, int64_t *info) {
+  uint8_t *alive = (uint8_t *)malloc((size_t)m + 1);
+  uint8_t *active = (uint8_t *)malloc((size_t)n + 1);
+  int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  int32_t *part = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * ((size_t)m + 1));
+  int32_t *phi_h = (int32_t *)malloc(sizeof(int32_t) * ((size_t)m + 1));
+  int32_t *sup_h = (int32_t *)malloc(sizeof(int32_t) * ((size_t)m + 1));
+  int64_t st[5] = {0, 0, 0, 0, 0};
+  adj_t g;
+  memset(&g, 0, sizeof(g));
+  int rc = OR_OK;
+  if (!alive || !active || !deg || !part || !order || !ids || !phi_h || !sup_h) { rc = -OR_NOMEM; goto out; }
+  if ((rc = adj_build(n, m, src, dst, &g))) goto out;
+  for (int64_t e = 0; e < m; ++e) { alive[e] = 1; lb[e] = 2; phi2[e] = 0; }  /* Step 1 */
+  int64_t left = m;
+  while (left > 0) {                                                          /* Step 2 */
+    const int first = st[0] == 0;
+    st[0]++;
+    for (int32_t v = 0; v < n; ++v) deg[v] = 0;
+    for (int64_t e = 0; e < m; ++e)
+      if (alive[e]) { deg[src[e]]++; deg[dst[e]]++; }
+    for (int32_t v = 0; v < n; ++v) active[v] = deg[v] > 0;
+    int64_t parts;                                                            /* Step 3 */
+    if (first && first_part) {
+      parts = 0;
+      for (int32_t v = 0; v < n; ++v) {
+        part[v] = active[v] ? first_part[v] : -1;
+        if (active[v] && first_part[v] < 0) { rc = -OR_INVAL; goto out; }
+        if (part[v] + 1 > parts) parts = part[v] + 1;
+      }
+    } else {
+      parts = grow_partition(&g, alive, deg, cap, part, order);
+      if (parts < 0) { rc = (int)parts; goto out; }
+    }
+    int64_t removed = 0;
+    for (int64_t p = 0; p < parts; ++p) {                                     /* Step 4 */
+      int64_t h = 0;                                                          /* Step 5: NS(P_p) */
+      for (int64_t e = 0; e < m; ++e)
+        if (alive[e] && (part[src[e]] == p || part[dst[e]] == p)) ids[h++] = e;
+      if (h == 0) continue;
+      if (h > cap) { rc = -OR_CAP; goto out; }
+      st[1]++;
+      if (h > st[4]) st[4] = h;
+      rc = local_truss(n, src, dst, ids, h, phi_h, sup_h);                    /* Step 6 */
+      if (rc) goto out;
+      for (int64_t i = 0; i < h; ++i) {
+        const int64_t e = ids[i];
+        if (phi_h[i] > lb[e]) lb[e] = phi_h[i];                               /* Step 7 */
+        if (part[src[e]] == p && part[dst[e]] == p) {                         /* internal */
+          if (first && sup_h[i] == 0) { phi2[e] = 1; st[2]++; }               /* Steps 8-9 */
+          else st[3]++;                                                       /* Step 10 */
+          alive[e] = 0;
+          ++removed;
+        }
+      }
+    }
+    if (removed == 0) { rc = -OR_STALL; goto out; }
+    left -= removed;
+  }
+  if (info) for (int i = 0; i < 5; ++i) info[i] = st[i];
+out:
+  adj_free(&g);
+  free(alive); free(active); free(deg); free(part); free(order); free(ids); free(phi_h); free(sup_h);
+  return rc;
+}
+
+/* Peel the eligible edges of the subgraph ids[0..h) at level k (Steps 1-5 of
+ * Procedure 5, Steps 7-11 of Procedure 9): while an eligible edge has support
+ * <= k-2, it joins Phi_k and the two other edges of each of its triangles in
+ * the subgraph lose one.  Removed edges get phi = k and gone = 1.  Returns the
+ * number of edges output, or a negative error. */
+static int64_t peel_level(int32_t n, const int32_t *src, const int32_t *dst, const int64_t *ids, int64_t h,
+                          const uint8_t *elig, int32_t k, int32_t *phi, uint8_t *gone) {
+  int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(h + 1));
+  int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)(h + 1));
+  int32_t *sup = (int32_t *)malloc(sizeof(int32_t) * (size_t)(h + 1));
+  uint8_t *out = (uint8_t *)calloc((size_t)h + 1, 1);
+  uint8_t *inq = (uint8_t *)calloc((size_t)h + 1, 1);
+  int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(h + 1));
+  adj_t g;
+  memset(&g, 0, sizeof(g));
+  int64_t count = 0;
+  if (!s || !d || !sup || !out || !inq || !queue) { count = -OR_NOMEM; goto done; }
+  for (int64_t i = 0; i < h; ++i) { s[i] = src[ids[i]]; d[i] = dst[ids[i]]; }
+  int rc = oracle_support_fwd(n, h, s, d, sup, NULL);                         /* Step 1 */
+  if (!rc) rc = adj_build(n, h, s, d, &g);
+  if (rc) { count = rc; goto done; }
+  int64_t qh = 0, qt = 0;
+  for (int64_t i = 0; i < h; ++i)
+    if (elig[i] && sup[i] <= k - 2) { queue[qt++] = i; inq[i] = 1; }
+  while (qh < qt) {                                                           /* Step 2 */
+    const int64_t e = queue[qh++];
+    const int32_t u = s[e], v = d[e];
+    for (int64_t j = g.off[u]; j < g.off[u + 1]; ++j) {                       /* Step 4 */
+      const int32_t w = g.nbr[j];
+      const int64_t euw = g.eid[j];
+      if (w == v || out[euw]) continue;
+      const int64_t q = find_nbr(&g, v, w);
+      if (q < 0 || out[g.eid[q]]) continue;
+      const int64_t f2[2] = {euw, g.eid[q]};
+      for (int t = 0; t < 2; ++t) {                                           /* Step 5 */
+        const int64_t f = f2[t];
+        sup[f] -= 1;
+        if (elig[f] && !inq[f] && sup[f] <= k - 2) { queue[qt++] = f; inq[f] = 1; }
+      }
+    }
+    out[e] = 1;                                                               /* Steps 3 and 6 */
+    phi[ids[e]] = k;
+    gone[ids[e]] = 1;
+    ++count;
+  }
+done:
+  adj_free(&g);
+  free(s); free(d); free(sup); free(out); free(inq); free(queue);
+  return count;
+}
+
+/* Procedure 9: Phi_k of the candidate subgraph ids[0..h) (internal[i] = both
+ * ends in U_k) when it exceeds cap.  Returns edges output or an error;
+ * scans_out accumulates the scans made. */
+static int64_t proc9(const adj_t *g, const int32_t *src, const int32_t *dst, const int64_t *ids, int64_t h,
+                     const uint8_t *internal, int32_t k, int64_t cap, int32_t *phi, uint8_t *gone,
+                     int64_t *scans_out) {
+  const int32_t n = g->n;
+  uint8_t *mask = (uint8_t *)calloc((size_t)g->m + 1, 1);   /* edges of H' (by edge id) */
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  uint8_t *inh = (uint8_t *)calloc((size_t)h + 1, 1);       /* still in H */
+  uint8_t *cov = (uint8_t *)calloc((size_t)h + 1, 1);       /* removed from H' */
+  int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  uint8_t *active = (uint8_t *)malloc((size_t)n + 1);
+  int32_t *part = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+  int64_t *fid = (int64_t *)malloc(sizeof(int64_t) * ((size_t)h + 1));
+  int64_t *fpos = (int64_t *)malloc(sizeof(int64_t) * ((size_t)h + 1));
+  uint8_t *elig = (uint8_t *)malloc((size_t)h + 1);
+  int64_t total = 0;
+  if (!mask || !order || !inh || !cov || !deg || !active || !part || !fid || !fpos || !elig) {
+    total = -OR_NOMEM;
+    goto done;
+  }
+  for (int64_t i = 0; i < h; ++i) inh[i] = 1;
+  for (;;) {                                                                  /* Steps 2-14 */
+    int64_t found = 0;
+    for (int64_t i = 0; i < h; ++i) cov[i] = !inh[i];                         /* Step 2: H' = H */
+    for (;;) {                                                                /* Step 3 */
+      int64_t left = 0;
+      for (int32_t v = 0; v < n; ++v) deg[v] = 0;
+      for (int64_t i = 0; i < h; ++i) {
+        mask[ids[i]] = inh[i] && !cov[i];
+        if (!inh[i]) continue;
+        deg[src[ids[i]]]++; deg[dst[ids[i]]]++;
+        left += !cov[i];
+      }
+      if (left == 0) break;
+      (*scans_out)++;
+      const int64_t parts = grow_partition(g, mask, deg, cap, part, order);  /* Step 4 */
+      if (parts < 0) { total = parts; goto done; }
+      int64_t covered = 0;
+      for (int64_t p = 0; p < parts; ++p) {                                   /* Step 5 */
+        int64_t f = 0;                                                        /* Step 6: F = NS(P_p) in H */
+        for (int64_t i = 0; i < h; ++i) {
+          if (!inh[i]) continue;
+          const int32_t a = part[src[ids[i]]], b = part[dst[ids[i]]];
+          if (a == p || b == p) { fpos[f] = i; fid[f] = ids[i]; elig[f] = a == p && b == p && internal[i]; ++f; }
+        }
+        if (f == 0) continue;
+        if (f > cap) { total = -OR_CAP; goto done; }
+        const int64_t c = peel_level(n, src, dst, fid, f, elig, k, phi, gone);  /* Steps 7-12 */
+        if (c < 0) { total = c; goto done; }
+        found += c;
+        for (int64_t j = 0; j < f; ++j) {
+          const int64_t i = fpos[j];
+          if (gone[ids[i]]) inh[i] = 0;
+          const int32_t a = part[src[ids[i]]], b = part[dst[ids[i]]];
+          if (a == p && b == p && !cov[i]) { cov[i] = 1; ++covered; }         /* Step 13 */
+        }
+      }
+      if (covered == 0) { total = -OR_STALL; goto done; }
+    }
+    total += found;
+    if (found == 0) break;                                                    /* Step 14 */
+  }
+done:
+  free(mask); free(order);
+  free(inh); free(cov); free(deg); free(active); free(part); free(fid); free(fpos); free(elig);
+  return total;
+}
+
+/* Algorithm 4 on the output of LowerBounding: phi[e] for every edge.
+ * kstart = 3, or 2 when LowerBounding took more than one pass.  info
+ * (nullable) = {candidate subgraphs, Procedure 9 calls, Procedure 9 scans,
+ * largest candidate subgraph, k_max}. */
+int oracle_bottom_up(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *lb,
+                     const uint8_t *phi2, int32_t kstart, int64_t cap, int32_t *phi, int64_t *info) {
+  uint8_t *gone = (uint8_t *)malloc((size_t)m + 1);
+  uint8_t *inu = (uint8_t *)malloc((size_t)n + 1);
+  int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * ((size_t)m + 1));
+  uint8_t *internal = (uint8_t *)malloc((size_t)m + 1);
+  int64_t st[5] = {0, 0, 0, 0, 0};
+  adj_t g;
+  memset(&g, 0, sizeof(g));
+  int rc = OR_OK;
+  if (!gone || !inu || !ids || !internal) { rc = -OR_NOMEM; goto out; }
+  if ((rc = adj_build(n, m, src, dst, &g))) goto out;
+  int64_t left = 0;
+  for (int64_t e = 0; e < m; ++e) {
+    gone[e] = phi2[e];
+    phi[e] = phi2[e] ? 2 : 0;
+    left += !phi2[e];
+  }
+  int32_t k = kstart;                                                         /* Step 2 */
+  while (left > 0) {                                                          /* Step 7 */
+    int32_t lmin = 0x7fffffff;
+    for (int64_t e = 0; e < m; ++e)
+      if (!gone[e] && lb[e] < lmin) lmin = lb[e];
+    if (lmin > k) k = lmin;
+    for (int32_t v = 0; v < n; ++v) inu[v] = 0;                               /* Step 3: U_k */
+    for (int64_t e = 0; e < m; ++e)
+      if (!gone[e] && lb[e] <= k) { inu[src[e]] = 1; inu[dst[e]] = 1; }
+    int64_t h = 0;                                                            /* Steps 4-5: NS(U_k) */
+    for (int64_t e = 0; e < m; ++e)
+      if (!gone[e] && (inu[src[e]] || inu[dst[e]])) {
+        internal[h] = inu[src[e]] && inu[dst[e]];
+        ids[h++] = e;
+      }
+    st[0]++;
+    if (h > st[3]) st[3] = h;
+    int64_t c;
+    if (h <= cap) {
+      c = peel_level(n, src, dst, ids, h, internal, k, phi, gone);            /* Step 6: Procedure 5 */
+    } else {
+      st[1]++;
+      c = proc9(&g, src, dst, ids, h, internal, k, cap, phi, gone, &st[2]);
+    }
+    if (c < 0) { rc = (int)c; goto out; }
+    left -= c;
+    st[4] = k;
+    k += 1;                                                                   /* Step 8 */
+  }
+  if (info) for (int i = 0; i < 5; ++i) info[i] = st[i];
+out:
+  adj_free(&g);
+  free(gone); free(inu); free(ids); free(internal);
+  return rc;
+}

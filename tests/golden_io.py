@@ -78,3 +78,31 @@ def oracle_record(name):
 def int32_digest(a):
     import hashlib
     return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+
+
+def example3():
+    """Example 3's fixture: dict with part (vertex -> 1..3), bound ((u, v) ->
+    value), phi2 (list of (u, v)) and classes (k -> list of (u, v)); (u, v)
+    with u < v."""
+    out = {"part": {}, "bound": {}, "phi2": [], "classes": {}}
+
+    def pair(t):
+        a, b = t.split("-")
+        u, v = _vid(a), _vid(b)
+        return (min(u, v), max(u, v))
+
+    with open(os.path.join(GOLDEN, "example3_bottomup.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            t = line.split()
+            if t[0] == "part":
+                out["part"][_vid(t[1])] = int(t[2])
+            elif t[0] == "bound":
+                out["bound"][pair(t[1])] = int(t[2])
+            elif t[0] == "phi2":
+                out["phi2"].extend(pair(x) for x in t[1:])
+            elif t[0] == "class":
+                out["classes"][int(t[1])] = [pair(x) for x in t[2:]]
+    return out
