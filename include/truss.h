@@ -265,6 +265,51 @@ int truss_cohesion_workspace_size(const truss_graph *g, size_t *bytes);
 int truss_cohesion(const truss_graph *g, const truss_options *opts, truss_cohesion_stats *out, void *ws,
                    size_t ws_bytes, void *stream);
 
+/* ---- bottom-up decomposition of a graph in host memory (Section 5) ------- */
+/* Host memory holds the graph, the bounds and the results (the paper's disk);
+ * the device holds one neighbourhood subgraph NS(P) (Definition 4) at a time
+ * (the paper's main memory), of at most `cap` edges.  LowerBounding
+ * (Algorithm 3) partitions the vertices of the shrinking graph into parts
+ * whose neighbourhood subgraphs fit, decomposes each on the device and keeps
+ * the largest local truss number of every edge as its lower bound (Lemma 1);
+ * Algorithm 4 then computes Phi_3, Phi_4, ... from the candidate subgraphs
+ * NS(U_k) by Procedure 5, or by Procedure 9 when a candidate exceeds cap.
+ * Parts are grown breadth-first from the smallest-id unplaced vertex, a
+ * vertex weighing its degree, a part's weight at most cap.  Only the first
+ * pass of Algorithm 3 sees the input graph, so only it outputs internal edges
+ * of support 0 as Phi_2; Algorithm 4 starts at k = 2 after a second pass. */
+typedef struct truss_bottomup_stats {
+  int64_t passes;        /* LowerBounding passes (Algorithm 3, Step 2)                */
+  int64_t subgraphs;     /* neighbourhood subgraphs decomposed by LowerBounding       */
+  int64_t phi2_edges;    /* |Phi_2| output by LowerBounding                           */
+  int64_t gnew_edges;    /* |G_new|                                                   */
+  int64_t max_subgraph;  /* most edges in one neighbourhood subgraph of LowerBounding  */
+  int64_t candidates;    /* candidate subgraphs NS(U_k) (Algorithm 4, Steps 3-5)      */
+  int64_t proc9_calls;   /* candidates above cap (Procedure 9)                        */
+  int64_t proc9_scans;   /* partitions of H' made by Procedure 9 (its Step 4)         */
+  int64_t max_candidate; /* most edges in a candidate subgraph                        */
+  int64_t device_calls;  /* subgraphs run on the device                               */
+  int64_t bytes_h2d, bytes_d2h;
+  int32_t kstart, kmax;  /* first k of Algorithm 4; largest truss number              */
+  double ms_lower, ms_bottomup, ms_total;
+} truss_bottomup_stats;
+
+/* Device workspace for a budget of cap edges per subgraph (1 <= cap <= INT32_MAX). */
+int truss_bottomup_workspace_size(int64_t cap, size_t *bytes);
+/* src, dst (host): the m edges over vertices 0..n-1 (validated: ids in range,
+ * no self-loop, no pair twice).  first_part (host, nullable): part id >= 0 of
+ * every vertex with an edge, for the first LowerBounding pass instead of the
+ * grown parts (each part's neighbourhood subgraph must fit in cap).
+ * truss_out (host) int32[m]: phi(e) by input index; lower_out (host,
+ * nullable) int32[m]: the bound from LowerBounding.  opts as for
+ * truss_decompose (nullable).  ws (device): truss_bottomup_workspace_size
+ * bytes.  Synchronises the stream; allocates pinned host staging of 17 bytes
+ * per budget edge for the call.  TRUSS_E_WORKSPACE when a vertex alone, a
+ * given part, or every part of a pass leaves no internal edge within cap. */
+int truss_bottomup(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *first_part,
+                   int64_t cap, int32_t *truss_out, int32_t *lower_out, const truss_options *opts,
+                   truss_bottomup_stats *stats, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- tracing: the per-decision record behind the learned scheduler ----- */
 /* Peeling level actions: bit 0 = probe (0 hash table, 1 binary search),
  * bit 1 = frontier mode (0 sparse worklist, 1 dense re-scan). */

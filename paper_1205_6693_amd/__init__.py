@@ -94,6 +94,17 @@ class CohesionStats(ctypes.Structure):
                 "V_C": self.v_c, "E_C": self.e_c, "cmax": self.cmax, "CC_C": self.cc_c}
 
 
+class BottomUpStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "passes", "subgraphs", "phi2_edges", "gnew_edges", "max_subgraph", "candidates", "proc9_calls",
+        "proc9_scans", "max_candidate", "device_calls", "bytes_h2d", "bytes_d2h")] + [
+        ("kstart", ctypes.c_int32), ("kmax", ctypes.c_int32), ("ms_lower", ctypes.c_double),
+        ("ms_bottomup", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -139,6 +150,9 @@ def load_library():
     lib.truss_core_numbers.argtypes = [gp, vp, ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
     lib.truss_cohesion_workspace_size.argtypes = [gp, szp]
     lib.truss_cohesion.argtypes = [gp, op, ctypes.POINTER(CohesionStats), vp, ctypes.c_size_t, vp]
+    lib.truss_bottomup_workspace_size.argtypes = [i64, szp]
+    lib.truss_bottomup.argtypes = [i32, i64, vp, vp, vp, i64, vp, vp, op, ctypes.POINTER(BottomUpStats), vp,
+                                   ctypes.c_size_t, vp]
     lib.truss_mlp_param_count.argtypes = [i32, i32, i32]
     lib.truss_mlp_workspace_size.argtypes = [i32, i32, i32, i32, szp]
     lib.truss_mlp_forward.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp, ctypes.c_size_t, vp]
@@ -154,7 +168,7 @@ def load_library():
               "truss_batch_plan_create", "truss_batch_plan_run", "truss_batch_autotune",
               "truss_upper_bound", "truss_topdown_workspace_size", "truss_topdown",
               "truss_core_workspace_size", "truss_core_numbers", "truss_cohesion_workspace_size",
-              "truss_cohesion",
+              "truss_cohesion", "truss_bottomup_workspace_size", "truss_bottomup",
               "truss_mlp_param_count", "truss_mlp_workspace_size", "truss_mlp_forward",
               "truss_mlp_backward", "truss_mlp_train", "truss_sched_part_floats",
               "truss_sched_model_floats", "truss_sched_train_workspace_size", "truss_sched_train"):
@@ -560,3 +574,31 @@ def truss_cohesion(graph: Graph, opts: Options | None = None, ws=None, stream=No
     _check(lib.truss_cohesion(ctypes.byref(g), ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
                               ws.numel(), _stream(stream)))
     return st.to_dict()
+
+
+def truss_bottomup(n: int, src, dst, cap: int, first_part=None, opts: Options | None = None, ws=None,
+                   stream=None):
+    """Bottom-up truss decomposition of a graph held in host memory (Section 5:
+    LowerBounding, then Algorithm 4 with Procedures 5 and 9), the device
+    holding one neighbourhood subgraph of at most `cap` edges at a time.
+    src, dst: host int32 arrays.  Returns (phi, lower bound, stats) as numpy
+    arrays and a dict."""
+    import numpy as np
+    torch = _torch()
+    lib = load_library()
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    m = src.size
+    fp = None if first_part is None else np.ascontiguousarray(first_part, dtype=np.int32)
+    if ws is None:
+        b = ctypes.c_size_t(0)
+        _check(lib.truss_bottomup_workspace_size(int(cap), ctypes.byref(b)))
+        ws = torch.empty(max(1, b.value), dtype=torch.uint8, device="cuda")
+    out = np.zeros(max(m, 1), dtype=np.int32)
+    low = np.zeros(max(m, 1), dtype=np.int32)
+    st = BottomUpStats()
+    _check(lib.truss_bottomup(int(n), m, src.ctypes.data, dst.ctypes.data,
+                              None if fp is None else fp.ctypes.data, int(cap), out.ctypes.data, low.ctypes.data,
+                              ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
+                              _stream(stream)))
+    return out[:m], low[:m], st.to_dict()

@@ -37,6 +37,19 @@ __global__ void k_scatter_sup(const int2* __restrict__ sr, const int32_t* __rest
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0; }
 
+// supports out of reach of every level for edges that must not be peeled
+constexpr int kFrozenSup = 1 << 29;
+__global__ void k_freeze(int2* __restrict__ sr, const int32_t* __restrict__ perm, const uint8_t* __restrict__ frozen,
+                         int64_t m) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < m && frozen[perm ? perm[e] : e]) sr[e].x = kFrozenSup;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ x, int64_t m, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < m) x[i] = v;
+}
+
 __global__ void k_sum_sup(const int2* __restrict__ sr, int64_t m, unsigned long long* total) {
   unsigned long long x = 0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
@@ -197,9 +210,10 @@ struct Timer {
 };
 
 // Runs build + support, then either scatters sup (want_truss false) or peels.
+// sub (nullable): the neighbourhood-subgraph extras of run_subgraph (decompose mode)
 int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles,
                const truss_options* opts_in, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s,
-               truss_trace* trace) {
+               truss_trace* trace, const SubgraphRun* sub = nullptr) {
   int rc = check_graph(g);
   if (rc) return rc;
   rc = validate_options(opts_in);
@@ -267,6 +281,16 @@ int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles
   } else {
     if (stats && g->m > 0) hipLaunchKernelGGL(k_sum_sup, dim3(1024), dim3(kT), 0, s, p.sr, g->m, p.d_total);
     int32_t* tc = g->fmt == TRUSS_FMT_EDGES ? p.truss_canon : out;
+    if (sub && g->m > 0) {
+      if (sub->sup_out)
+        hipLaunchKernelGGL(k_scatter_sup, dim3(grid_for(g->m)), dim3(kT), 0, s, p.sr, dg.perm, g->m, sub->sup_out,
+                           p.d_total);
+      if (sub->frozen)
+        hipLaunchKernelGGL(k_freeze, dim3(grid_for(g->m)), dim3(kT), 0, s, p.sr, dg.perm, sub->frozen, g->m);
+      if (sub->stop_level > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(g->m)), dim3(kT), 0, s, tc, g->m, 0);
+      pp.first_level = sub->first_level;
+      pp.stop_level = sub->stop_level;
+    }
     rc = peel(dg, pp, p.sr, tc, a, &pr, s, trace);
     if (rc) return rc;
     if (g->fmt == TRUSS_FMT_EDGES && g->m > 0)
@@ -326,11 +350,6 @@ __global__ void k_select(const int32_t* __restrict__ psi, const int32_t* __restr
     sdst[pos] = ev[e];
     sid[pos] = (int32_t)e;
   }
-}
-
-__global__ void k_fill_i32(int32_t* __restrict__ x, int64_t m, int32_t v) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < m) x[i] = v;
 }
 
 // truss numbers of the subgraph at or above kmin, written to the caller's indexing
@@ -761,6 +780,31 @@ int run_cohesion(const truss_graph* g, const truss_options* opts, truss_cohesion
 }
 
 }  // namespace
+
+size_t subgraph_workspace(int32_t n, int64_t m) {
+  truss_graph sg;
+  memset(&sg, 0, sizeof(sg));
+  sg.fmt = TRUSS_FMT_EDGES;
+  sg.n = n;
+  sg.m = m;
+  sg.src = sg.dst = reinterpret_cast<const int32_t*>(1);
+  Arena a;
+  a.counting = true;
+  Plan p;
+  layout(&sg, a, p, nullptr);
+  return a.used;
+}
+
+int run_subgraph(const SubgraphRun& r, const truss_options* opts, void* ws, size_t ws_bytes, hipStream_t s) {
+  truss_graph sg;
+  memset(&sg, 0, sizeof(sg));
+  sg.fmt = TRUSS_FMT_EDGES;
+  sg.n = r.n;
+  sg.m = r.m;
+  sg.src = r.src;
+  sg.dst = r.dst;
+  return run_single(&sg, kModeDecompose, r.truss_out, nullptr, opts, nullptr, ws, ws_bytes, s, nullptr, &r);
+}
 
 void set_last_error(const char* fmt, ...) {
   va_list ap;

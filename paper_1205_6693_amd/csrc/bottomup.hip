@@ -1,0 +1,628 @@
+// Bottom-up truss decomposition of a graph held in host memory (Section 5):
+// LowerBounding (Algorithm 3), then Algorithm 4 with Procedure 5, or
+// Procedure 9 (Appendix) when a candidate subgraph exceeds the budget.
+//
+// Host memory plays the part of the paper's disk and the device that of its
+// main memory: the graph, the bounds and the outputs stay on the host, and
+// each neighbourhood subgraph NS(P) (Definition 4) is relabelled, copied to
+// the device and decomposed there by the in-memory path.  The budget is the
+// most edges a subgraph sent to the device may hold.
+//
+// Partition of a vertex set (Step 3 of Algorithm 3, Step 4 of Procedure 9):
+// parts are grown breadth-first over the edges of the graph being partitioned
+// (the current G; H' in Procedure 9).  A part starts at the smallest-id
+// unplaced vertex that has such an edge and takes, from each vertex it holds
+// in the order added, every unplaced neighbour (ascending id) whose weight
+// still fits; when its growth stops it goes on from the next such vertex by id
+// if that one fits, else a new part starts there.  A vertex weighs its degree
+// in the graph the subgraphs are taken from, so |NS(P)| <= the part's weight
+// sum <= the budget.
+//
+// The 2-class: only the first pass of Algorithm 3 sees the input graph, so
+// only there does an internal edge of support 0 go to Phi_2; internal edges of
+// later passes go to G_new with their bound, and Algorithm 4 then starts at
+// k = 2.  Algorithm 4 skips each k for which no remaining edge has a bound
+// <= k (U_k and Phi_k are empty there).
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace truss {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// The input graph on the host: rows sorted by neighbour id, with edge ids.
+struct HostGraph {
+  int32_t n = 0;
+  int64_t m = 0;
+  const int32_t* src = nullptr;
+  const int32_t* dst = nullptr;
+  std::vector<int64_t> off;
+  std::vector<int32_t> nbr, eid;
+};
+
+int build_host_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, HostGraph& g) {
+  g.n = n;
+  g.m = m;
+  g.src = src;
+  g.dst = dst;
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t u = src[e], v = dst[e];
+    if (u < 0 || u >= n || v < 0 || v >= n) {
+      set_last_error("edge %lld has an endpoint outside [0, n)", (long long)e);
+      return TRUSS_E_RANGE;
+    }
+    if (u == v) {
+      set_last_error("edge %lld is a self-loop", (long long)e);
+      return TRUSS_E_SELFLOOP;
+    }
+  }
+  g.off.assign((size_t)n + 1, 0);
+  for (int64_t e = 0; e < m; ++e) {
+    g.off[(size_t)src[e] + 1]++;
+    g.off[(size_t)dst[e] + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) g.off[(size_t)v + 1] += g.off[v];
+  // rows in edge order, then transposed row by row: row y receives its
+  // neighbours x in ascending x
+  std::vector<int32_t> tn((size_t)(2 * m)), te((size_t)(2 * m));
+  std::vector<int64_t> fill(g.off.begin(), g.off.end() - 1);
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t u = src[e], v = dst[e];
+    tn[(size_t)fill[u]] = v;
+    te[(size_t)fill[u]++] = (int32_t)e;
+    tn[(size_t)fill[v]] = u;
+    te[(size_t)fill[v]++] = (int32_t)e;
+  }
+  g.nbr.resize((size_t)(2 * m));
+  g.eid.resize((size_t)(2 * m));
+  std::copy(g.off.begin(), g.off.end() - 1, fill.begin());
+  for (int32_t x = 0; x < n; ++x)
+    for (int64_t j = g.off[x]; j < g.off[(size_t)x + 1]; ++j) {
+      const int32_t y = tn[(size_t)j];
+      g.nbr[(size_t)fill[y]] = x;
+      g.eid[(size_t)fill[y]++] = te[(size_t)j];
+    }
+  for (int32_t v = 0; v < n; ++v)
+    for (int64_t j = g.off[v] + 1; j < g.off[(size_t)v + 1]; ++j)
+      if (g.nbr[(size_t)j] == g.nbr[(size_t)j - 1]) {
+        set_last_error("edge (%d, %d) is given twice", v, g.nbr[(size_t)j]);
+        return TRUSS_E_DUP;
+      }
+  return TRUSS_OK;
+}
+
+// A partition: vertices in placement order, part p = order[start[p] .. start[p+1]).
+struct Parts {
+  std::vector<int32_t> part;   // n: part id, -1 if not placed
+  std::vector<int32_t> order;  // placed vertices, part by part
+  std::vector<int64_t> start;  // parts + 1
+  int64_t count() const { return (int64_t)start.size() - 1; }
+};
+
+// Parts grown breadth-first (see the file comment).  mask: by edge id, the
+// edges of the graph being partitioned.  Returns false if a vertex alone
+// weighs more than cap.
+bool grow_parts(const HostGraph& g, const uint8_t* mask, const int64_t* w, int64_t cap, Parts& P) {
+  P.part.assign((size_t)g.n, -1);
+  P.order.clear();
+  P.start.assign(1, 0);
+  int64_t sum = 0, parts = 0;
+  for (int32_t r = 0; r < g.n; ++r) {
+    if (P.part[r] >= 0) continue;
+    bool has = false;
+    for (int64_t j = g.off[r]; j < g.off[(size_t)r + 1] && !has; ++j) has = mask[g.eid[(size_t)j]] != 0;
+    if (!has) continue;
+    if (w[r] > cap) {
+      set_last_error("vertex %d alone needs %lld edges, more than the budget of %lld", r, (long long)w[r],
+                     (long long)cap);
+      return false;
+    }
+    if (parts == 0 || sum + w[r] > cap) {  // a new part starts at r
+      if (parts > 0) P.start.push_back((int64_t)P.order.size());
+      parts += 1;
+      sum = 0;
+    }
+    const int32_t p = (int32_t)(parts - 1);
+    size_t head = P.order.size();
+    sum += w[r];
+    P.part[r] = p;
+    P.order.push_back(r);
+    while (head < P.order.size()) {
+      const int32_t v = P.order[head++];
+      for (int64_t j = g.off[v]; j < g.off[(size_t)v + 1]; ++j) {
+        const int32_t x = g.nbr[(size_t)j];
+        if (!mask[g.eid[(size_t)j]] || P.part[x] >= 0 || sum + w[x] > cap) continue;
+        P.part[x] = p;
+        sum += w[x];
+        P.order.push_back(x);
+      }
+    }
+  }
+  if (parts > 0) P.start.push_back((int64_t)P.order.size());
+  return true;
+}
+
+// A subgraph sent to the device: global edge ids and relabelled endpoints.
+struct Staged {
+  std::vector<int32_t> ids;  // global edge ids, in staging order
+  std::vector<uint8_t> flag;  // per staged edge (meaning set by the caller)
+};
+
+// Device side: staging buffers and the subgraph workspace, carved from the
+// caller's workspace; pinned host mirrors.
+struct Device {
+  int64_t cap = 0;
+  int32_t *d_src = nullptr, *d_dst = nullptr, *d_out = nullptr, *d_sup = nullptr;
+  uint8_t* d_frozen = nullptr;
+  void* sub_ws = nullptr;
+  size_t sub_bytes = 0;
+  int32_t *h_src = nullptr, *h_dst = nullptr, *h_out = nullptr, *h_sup = nullptr;
+  uint8_t* h_frozen = nullptr;
+  std::vector<int32_t> lid;      // n: local id of a vertex in the current subgraph, -1 otherwise
+  std::vector<int32_t> touched;  // vertices with a local id
+  int64_t calls = 0, h2d = 0, d2h = 0;
+  ~Device() {
+    if (h_src) (void)hipHostFree(h_src);
+  }
+};
+
+size_t device_layout(int64_t cap, Arena& a, Device* d) {
+  const size_t c = (size_t)(cap > 0 ? cap : 1);
+  int32_t* s = a.take<int32_t>(c);
+  int32_t* t = a.take<int32_t>(c);
+  int32_t* o = a.take<int32_t>(c);
+  int32_t* p = a.take<int32_t>(c);
+  uint8_t* f = a.take<uint8_t>(c);
+  const size_t sub = subgraph_workspace((int32_t)std::min<int64_t>(2 * cap + 1, 0x7fffffff), cap);
+  char* w = a.take<char>(sub);
+  if (d) {
+    d->d_src = s;
+    d->d_dst = t;
+    d->d_out = o;
+    d->d_sup = p;
+    d->d_frozen = f;
+    d->sub_ws = w;
+    d->sub_bytes = sub;
+  }
+  return a.used;
+}
+
+// Relabels the staged edges, copies them to the device, runs the subgraph
+// and brings back the per-edge truss level (and supports when want_sup).
+int run_staged(const HostGraph& g, Device& D, const Staged& S, bool frozen, int first_level, int stop_level,
+               bool want_sup, const truss_options* opts, hipStream_t s) {
+  const int64_t h = (int64_t)S.ids.size();
+  int32_t nl = 0;
+  for (int64_t i = 0; i < h; ++i) {
+    const int32_t e = S.ids[(size_t)i];
+    const int32_t u = g.src[e], v = g.dst[e];
+    if (D.lid[u] < 0) {
+      D.lid[u] = nl++;
+      D.touched.push_back(u);
+    }
+    if (D.lid[v] < 0) {
+      D.lid[v] = nl++;
+      D.touched.push_back(v);
+    }
+    D.h_src[i] = D.lid[u];
+    D.h_dst[i] = D.lid[v];
+    if (frozen) D.h_frozen[i] = S.flag[(size_t)i] ? 0 : 1;
+  }
+  for (int32_t v : D.touched) D.lid[v] = -1;
+  D.touched.clear();
+  const size_t b = sizeof(int32_t) * (size_t)h;
+  TRUSS_HIP(hipMemcpyAsync(D.d_src, D.h_src, b, hipMemcpyHostToDevice, s));
+  TRUSS_HIP(hipMemcpyAsync(D.d_dst, D.h_dst, b, hipMemcpyHostToDevice, s));
+  D.h2d += 2 * (int64_t)b;
+  if (frozen) {
+    TRUSS_HIP(hipMemcpyAsync(D.d_frozen, D.h_frozen, (size_t)h, hipMemcpyHostToDevice, s));
+    D.h2d += h;
+  }
+  SubgraphRun r;
+  r.src = D.d_src;
+  r.dst = D.d_dst;
+  r.n = nl;
+  r.m = h;
+  r.truss_out = D.d_out;
+  r.sup_out = want_sup ? D.d_sup : nullptr;
+  r.frozen = frozen ? D.d_frozen : nullptr;
+  r.first_level = first_level;
+  r.stop_level = stop_level;
+  const int rc = run_subgraph(r, opts, D.sub_ws, D.sub_bytes, s);
+  if (rc) return rc;
+  TRUSS_HIP(hipMemcpyAsync(D.h_out, D.d_out, b, hipMemcpyDeviceToHost, s));
+  D.d2h += (int64_t)b;
+  if (want_sup) {
+    TRUSS_HIP(hipMemcpyAsync(D.h_sup, D.d_sup, b, hipMemcpyDeviceToHost, s));
+    D.d2h += (int64_t)b;
+  }
+  TRUSS_HIP(hipStreamSynchronize(s));
+  D.calls += 1;
+  return TRUSS_OK;
+}
+
+struct Run {
+  const HostGraph& g;
+  Device& D;
+  const truss_options* opts;
+  hipStream_t s;
+  int64_t cap;
+  int32_t* truss;  // host output
+  truss_bottomup_stats st;
+};
+
+// ---- LowerBounding (Algorithm 3) -------------------------------------------------
+int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, std::vector<uint8_t>& phi2) {
+  const HostGraph& g = R.g;
+  std::vector<uint8_t> alive((size_t)g.m, 1);
+  std::vector<int64_t> deg((size_t)g.n);
+  for (int32_t v = 0; v < g.n; ++v) deg[v] = g.off[(size_t)v + 1] - g.off[v];
+  lb.assign((size_t)g.m, 2);  // Step 1 (the bound starts at 2, as in Example 3)
+  phi2.assign((size_t)g.m, 0);
+  Parts P;
+  Staged S;
+  int64_t left = g.m;
+  while (left > 0) {  // Step 2
+    const bool first = R.st.passes == 0;
+    R.st.passes += 1;
+    if (first && first_part) {  // Step 3: the caller's partition
+      int32_t parts = 0;
+      P.part.assign((size_t)g.n, -1);
+      for (int32_t v = 0; v < g.n; ++v) {
+        if (deg[v] == 0) continue;
+        if (first_part[v] < 0) {
+          set_last_error("vertex %d has edges but no part", v);
+          return TRUSS_E_INVAL;
+        }
+        P.part[v] = first_part[v];
+        parts = std::max(parts, first_part[v] + 1);
+      }
+      std::vector<int64_t> cnt((size_t)parts + 1, 0);
+      for (int32_t v = 0; v < g.n; ++v)
+        if (P.part[v] >= 0) cnt[(size_t)P.part[v] + 1]++;
+      for (int32_t p = 0; p < parts; ++p) cnt[(size_t)p + 1] += cnt[p];
+      P.start = cnt;
+      P.order.assign((size_t)cnt[(size_t)parts], 0);
+      for (int32_t v = 0; v < g.n; ++v)
+        if (P.part[v] >= 0) P.order[(size_t)cnt[P.part[v]]++] = v;
+    } else if (!grow_parts(g, alive.data(), deg.data(), R.cap, P)) {  // Step 3
+      return TRUSS_E_WORKSPACE;
+    }
+    int64_t removed = 0;
+    for (int64_t p = 0; p < P.count(); ++p) {  // Step 4
+      // Step 5: H = NS(P_p) in the current G; flag = internal
+      S.ids.clear();
+      S.flag.clear();
+      for (int64_t i = P.start[(size_t)p]; i < P.start[(size_t)p + 1]; ++i) {
+        const int32_t v = P.order[(size_t)i];
+        for (int64_t j = g.off[v]; j < g.off[(size_t)v + 1]; ++j) {
+          const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
+          if (!alive[(size_t)e]) continue;
+          const bool inside = P.part[w] == p;
+          if (inside && w < v) continue;  // listed from its smaller end
+          S.ids.push_back(e);
+          S.flag.push_back(inside ? 1 : 0);
+        }
+      }
+      const int64_t h = (int64_t)S.ids.size();
+      if (h == 0) continue;
+      if (h > R.cap) {
+        set_last_error("the neighbourhood subgraph of part %lld has %lld edges, more than the budget of %lld",
+                       (long long)p, (long long)h, (long long)R.cap);
+        return TRUSS_E_WORKSPACE;
+      }
+      R.st.subgraphs += 1;
+      R.st.max_subgraph = std::max(R.st.max_subgraph, h);
+      int rc = run_staged(g, R.D, S, false, 2, 0, true, R.opts, R.s);  // Step 6
+      if (rc) return rc;
+      for (int64_t i = 0; i < h; ++i) {
+        const int32_t e = S.ids[(size_t)i];
+        lb[(size_t)e] = std::max(lb[(size_t)e], R.D.h_out[i]);  // Step 7
+        if (!S.flag[(size_t)i]) continue;
+        if (first && R.D.h_sup[i] == 0) {  // Steps 8-9
+          phi2[(size_t)e] = 1;
+          R.st.phi2_edges += 1;
+        } else {  // Step 10
+          R.st.gnew_edges += 1;
+        }
+        alive[(size_t)e] = 0;
+        deg[g.src[e]] -= 1;
+        deg[g.dst[e]] -= 1;
+        removed += 1;
+      }
+    }
+    if (removed == 0) {
+      set_last_error("no part holds an internal edge: the budget of %lld edges is too small for this graph",
+                     (long long)R.cap);
+      return TRUSS_E_WORKSPACE;
+    }
+    left -= removed;
+  }
+  return TRUSS_OK;
+}
+
+// ---- Algorithm 4 -------------------------------------------------------------------
+struct BottomUp {
+  Run& R;
+  std::vector<uint8_t> gone;
+  std::vector<int32_t> cnt;  // per vertex: remaining edges with bound <= k (U_k = cnt > 0)
+  int64_t left = 0, active_left = 0;
+
+  void output(int32_t e, int32_t k) {
+    R.truss[e] = k;
+    gone[(size_t)e] = 1;
+    left -= 1;
+    active_left -= 1;
+    cnt[R.g.src[e]] -= 1;
+    cnt[R.g.dst[e]] -= 1;
+  }
+};
+
+// Procedure 5 on the candidate subgraph H (flag = internal).
+int procedure5(BottomUp& B, const Staged& H, int32_t k, int64_t* found) {
+  int rc = run_staged(B.R.g, B.R.D, H, true, k, k, false, B.R.opts, B.R.s);
+  if (rc) return rc;
+  for (size_t i = 0; i < H.ids.size(); ++i)
+    if (H.flag[i] && B.R.D.h_out[i] == k) {
+      B.output(H.ids[i], k);
+      *found += 1;
+    }
+  return TRUSS_OK;
+}
+
+// Procedure 9: H exceeds the budget; its internal edges are examined part by
+// part until a whole scan adds nothing to Phi_k.
+int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& hidx, int64_t* found_total) {
+  Run& R = B.R;
+  const HostGraph& g = R.g;
+  const size_t h = H.ids.size();
+  std::vector<uint8_t> inh(h, 1), cov(h, 0), mask((size_t)g.m, 0);
+  std::vector<int64_t> deg((size_t)g.n, 0);
+  for (size_t i = 0; i < h; ++i) hidx[(size_t)H.ids[i]] = (int32_t)i;
+  Parts P;
+  Staged F;
+  int rc = TRUSS_OK;
+  R.st.proc9_calls += 1;
+  for (;;) {  // Steps 2-14
+    int64_t found = 0;
+    for (size_t i = 0; i < h; ++i) cov[i] = !inh[i];  // Step 2: H' = H
+    for (;;) {                                        // Step 3
+      int64_t left = 0;
+      std::fill(deg.begin(), deg.end(), 0);
+      for (size_t i = 0; i < h; ++i) {
+        const int32_t e = H.ids[i];
+        mask[(size_t)e] = inh[i] && !cov[i];
+        if (!inh[i]) continue;
+        deg[g.src[e]] += 1;
+        deg[g.dst[e]] += 1;
+        left += !cov[i];
+      }
+      if (left == 0) break;
+      R.st.proc9_scans += 1;
+      if (!grow_parts(g, mask.data(), deg.data(), R.cap, P)) {  // Step 4
+        rc = TRUSS_E_WORKSPACE;
+        goto done;
+      }
+      int64_t covered = 0;
+      for (int64_t p = 0; p < P.count(); ++p) {  // Step 5
+        // Step 6: F = NS(P_p) in the current H; flag = eligible (internal to F and to H)
+        F.ids.clear();
+        F.flag.clear();
+        for (int64_t q = P.start[(size_t)p]; q < P.start[(size_t)p + 1]; ++q) {
+          const int32_t v = P.order[(size_t)q];
+          for (int64_t j = g.off[v]; j < g.off[(size_t)v + 1]; ++j) {
+            const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
+            const int32_t i = hidx[(size_t)e];
+            if (i < 0 || !inh[(size_t)i]) continue;
+            const bool inside = P.part[w] == p;
+            if (inside && w < v) continue;
+            F.ids.push_back(e);
+            F.flag.push_back(inside && H.flag[(size_t)i] ? 1 : 0);
+          }
+        }
+        if (F.ids.empty()) continue;
+        rc = run_staged(g, R.D, F, true, k, k, false, R.opts, R.s);  // Steps 7-11
+        if (rc) goto done;
+        for (size_t j = 0; j < F.ids.size(); ++j) {
+          const int32_t e = F.ids[j];
+          const int32_t i = hidx[(size_t)e];
+          if (F.flag[j] && R.D.h_out[j] == k) {  // Step 12
+            B.output(e, k);
+            inh[(size_t)i] = 0;
+            found += 1;
+          }
+          if (P.part[g.src[e]] == p && P.part[g.dst[e]] == p && !cov[(size_t)i]) {  // Step 13
+            cov[(size_t)i] = 1;
+            covered += 1;
+          }
+        }
+      }
+      if (covered == 0) {
+        set_last_error("procedure 9 made no progress: the budget of %lld edges is too small", (long long)R.cap);
+        rc = TRUSS_E_WORKSPACE;
+        goto done;
+      }
+    }
+    *found_total += found;
+    if (found == 0) break;  // Step 14
+  }
+done:
+  for (size_t i = 0; i < h; ++i) hidx[(size_t)H.ids[i]] = -1;
+  return rc;
+}
+
+int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>& phi2) {
+  const HostGraph& g = R.g;
+  BottomUp B{R, {}, {}, 0, 0};
+  B.gone.assign((size_t)g.m, 0);
+  B.cnt.assign((size_t)g.n, 0);
+  int32_t maxlb = 2;
+  for (int64_t e = 0; e < g.m; ++e) {
+    if (phi2[(size_t)e]) {
+      B.gone[(size_t)e] = 1;
+      R.truss[e] = 2;
+    } else {
+      R.truss[e] = 0;
+      B.left += 1;
+      maxlb = std::max(maxlb, lb[(size_t)e]);
+    }
+  }
+  // G_new's edges by bound (counting sort); activated in that order as k grows
+  std::vector<int64_t> byb((size_t)maxlb + 2, 0);
+  for (int64_t e = 0; e < g.m; ++e)
+    if (!phi2[(size_t)e]) byb[(size_t)lb[(size_t)e] + 1]++;
+  for (int32_t b = 0; b <= maxlb; ++b) byb[(size_t)b + 1] += byb[b];
+  std::vector<int32_t> sorted((size_t)B.left);
+  for (int64_t e = 0; e < g.m; ++e)
+    if (!phi2[(size_t)e]) sorted[(size_t)byb[lb[(size_t)e]]++] = (int32_t)e;
+  std::vector<int32_t> ulist, hidx((size_t)g.m, -1);
+  std::vector<uint8_t> inlist((size_t)g.n, 0);
+  size_t ap = 0;
+  Staged H;
+  int32_t k = R.st.kstart;  // Step 2
+  while (B.left > 0) {      // Step 7
+    // Step 3: U_k = ends of the remaining edges with bound <= k
+    for (;;) {
+      while (ap < sorted.size() && lb[(size_t)sorted[ap]] <= k) {
+        const int32_t e = sorted[ap++];
+        for (const int32_t v : {g.src[e], g.dst[e]}) {
+          if (B.cnt[v]++ == 0 && !inlist[v]) {
+            inlist[v] = 1;
+            ulist.push_back(v);
+          }
+        }
+        B.active_left += 1;
+      }
+      if (B.active_left > 0) break;
+      k = lb[(size_t)sorted[ap]];  // no candidate at this k: Phi_k is empty
+    }
+    // Steps 4-5: H = NS(U_k); flag = internal
+    size_t keep = 0;
+    for (size_t i = 0; i < ulist.size(); ++i) {
+      const int32_t u = ulist[i];
+      if (B.cnt[u] > 0) ulist[keep++] = u;
+      else inlist[u] = 0;
+    }
+    ulist.resize(keep);
+    H.ids.clear();
+    H.flag.clear();
+    for (const int32_t u : ulist)
+      for (int64_t j = g.off[u]; j < g.off[(size_t)u + 1]; ++j) {
+        const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
+        if (B.gone[(size_t)e]) continue;
+        const bool inside = B.cnt[w] > 0;
+        if (inside && w < u) continue;
+        H.ids.push_back(e);
+        H.flag.push_back(inside ? 1 : 0);
+      }
+    R.st.candidates += 1;
+    R.st.max_candidate = std::max(R.st.max_candidate, (int64_t)H.ids.size());
+    int64_t found = 0;
+    const int rc = (int64_t)H.ids.size() <= R.cap ? procedure5(B, H, k, &found)  // Step 6
+                                                   : procedure9(B, H, k, hidx, &found);
+    if (rc) return rc;
+    if (found > 0) R.st.kmax = k;
+    k += 1;  // Step 8
+  }
+  return TRUSS_OK;
+}
+
+}  // namespace
+
+}  // namespace truss
+
+using namespace truss;
+
+extern "C" {
+
+int truss_bottomup_workspace_size(int64_t cap, size_t* bytes) {
+  if (!bytes || cap < 1) {
+    set_last_error(!bytes ? "bytes is NULL" : "the budget must be at least one edge");
+    return TRUSS_E_INVAL;
+  }
+  if (cap > 0x7fffffffLL) {
+    set_last_error("the budget exceeds INT32_MAX edges");
+    return TRUSS_E_TOOBIG;
+  }
+  Arena a;
+  a.counting = true;
+  *bytes = device_layout(cap, a, nullptr);
+  return TRUSS_OK;
+}
+
+int truss_bottomup(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const int32_t* first_part,
+                   int64_t cap, int32_t* truss_out, int32_t* lower_out, const truss_options* opts,
+                   truss_bottomup_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  const auto t0 = Clock::now();
+  if (n < 0 || m < 0 || (m > 0 && (!src || !dst || !truss_out))) {
+    set_last_error("invalid graph or NULL output");
+    return TRUSS_E_INVAL;
+  }
+  if (m > 0x7fffffffLL) {
+    set_last_error("m exceeds INT32_MAX");
+    return TRUSS_E_TOOBIG;
+  }
+  int rc = validate_options(opts);
+  if (rc) return rc;
+  size_t need = 0;
+  if ((rc = truss_bottomup_workspace_size(cap, &need))) return rc;
+  if (!ws || ws_bytes < need) {
+    set_last_error("workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    return TRUSS_E_WORKSPACE;
+  }
+  truss_bottomup_stats st;
+  memset(&st, 0, sizeof(st));
+  if (stats) *stats = st;
+  HostGraph g;
+  if ((rc = build_host_graph(n, m, src, dst, g))) return rc;
+  Device D;
+  D.cap = cap;
+  Arena a;
+  a.base = static_cast<char*>(ws);
+  a.cap = ws_bytes;
+  device_layout(cap, a, &D);
+  const size_t c = (size_t)cap;
+  void* pin = nullptr;
+  if (hipHostMalloc(&pin, c * (4 * sizeof(int32_t) + 1), hipHostMallocDefault) != hipSuccess) {
+    set_last_error("pinned staging of %zu bytes failed", c * (4 * sizeof(int32_t) + 1));
+    return TRUSS_E_NOMEM;
+  }
+  D.h_src = static_cast<int32_t*>(pin);
+  D.h_dst = D.h_src + c;
+  D.h_out = D.h_dst + c;
+  D.h_sup = D.h_out + c;
+  D.h_frozen = reinterpret_cast<uint8_t*>(D.h_sup + c);
+  D.lid.assign((size_t)n, -1);
+  Run R{g, D, opts, (hipStream_t)stream, cap, truss_out, st};
+  std::vector<int32_t> lb;
+  std::vector<uint8_t> phi2;
+  const auto t1 = Clock::now();
+  if ((rc = lower_bounding(R, first_part, lb, phi2))) return rc;
+  R.st.ms_lower = ms_since(t1);
+  if (lower_out)
+    for (int64_t e = 0; e < m; ++e) lower_out[e] = lb[(size_t)e];
+  R.st.kstart = R.st.passes > 1 ? 2 : 3;
+  const auto t2 = Clock::now();
+  if ((rc = bottom_up(R, lb, phi2))) return rc;
+  R.st.ms_bottomup = ms_since(t2);
+  R.st.device_calls = D.calls;
+  R.st.bytes_h2d = D.h2d;
+  R.st.bytes_d2h = D.d2h;
+  R.st.ms_total = ms_since(t0);
+  if (R.st.kmax == 0 && m > 0) R.st.kmax = 2;
+  if (stats) *stats = R.st;
+  return TRUSS_OK;
+}
+
+}  // extern "C"

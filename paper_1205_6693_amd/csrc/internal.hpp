@@ -86,6 +86,8 @@ struct PeelPlan {
   const float* model = nullptr;       // (device) peeling model part when learned
   long long max_subrounds = 0;
   int grid_blocks = 0;
+  int first_level = 2;  // the first level peeled takes every live edge with sup <= first_level - 2
+  int stop_level = 0;   // > 0: stop once the next level would exceed it (later edges keep no truss number)
 };
 
 // Support: sr[e].x = sup(e) for every canonical edge (sr must be zeroed inside).
@@ -122,6 +124,28 @@ int compute_core_numbers(const DevGraph& dg, int32_t* core, int32_t* cmax_out, A
 // subgraph.  Syncs the stream.
 int subgraph_vertex_stats(int32_t n, const int32_t* su, const int32_t* sv, const int32_t* sup, int64_t ms, Arena& a,
                           double* nv_out, double* cc_out, hipStream_t s);
+
+// One neighbourhood subgraph on the device, given as a device edge list of m
+// edges over vertices 0..n-1 (validated like truss_decompose's input).
+// Outputs are indexed like the edge list.  sup_out (nullable): sup(e) in the
+// subgraph.  frozen (nullable, one byte per edge): a frozen edge is never
+// peeled (its support is set out of reach before peeling).  Peeling starts at
+// first_level and stops after stop_level (0: all levels); truss_out holds the
+// level at which each peeled edge left, 0 for edges never peeled when
+// stop_level > 0.  ws: subgraph_workspace(n, m) bytes.
+struct SubgraphRun {
+  const int32_t* src = nullptr;
+  const int32_t* dst = nullptr;
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t* truss_out = nullptr;
+  int32_t* sup_out = nullptr;
+  const uint8_t* frozen = nullptr;
+  int first_level = 2;
+  int stop_level = 0;
+};
+size_t subgraph_workspace(int32_t n, int64_t m);
+int run_subgraph(const SubgraphRun& r, const truss_options* opts, void* ws, size_t ws_bytes, hipStream_t s);
 
 void set_last_error(const char* fmt, ...);
 int validate_options(const truss_options* o);  // TRUSS_OK or TRUSS_E_INVAL (message set)

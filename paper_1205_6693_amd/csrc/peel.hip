@@ -125,6 +125,7 @@ struct alignas(256) PeelCtl {
   int sched;               // TRUSS_SCHED_* in effect
   int fix_bits, fix_vals;  // action bits fixed by the options
   int m_edges;
+  int stop_level;          // > 0: no level above it is started
   long long lvl_sub0;      // sub-rounds before the current level
   long long prev_sub;      // sub-rounds of the previous level
   unsigned long long t_dec;  // wall clock at the current level's decision
@@ -217,6 +218,7 @@ __device__ void control_step(PeelCtl* c, const PeelArgs& P) {
   const int sched = ldc(&c->sched);
   const int fix_bits = ldc(&c->fix_bits);
   const int fix_vals = ldc(&c->fix_vals);
+  const int stop_level = ldc(&c->stop_level);
   long long lvl_sub0 = ldc(&c->lvl_sub0);
   long long prev_sub = ldc(&c->prev_sub);
   unsigned long long t_dec = ldc(&c->t_dec);
@@ -300,7 +302,7 @@ __device__ void control_step(PeelCtl* c, const PeelArgs& P) {
       acnt = w_alive;
       acur ^= 1;
       first_out = 0;
-      if (w_alive == 0) {
+      if (w_alive == 0 || (stop_level > 0 && (w_qlen > 0 ? k + 1 : w_minsup + 2) > stop_level)) {
         phase = PH_DONE;
         break;
       }
@@ -983,7 +985,7 @@ __global__ void __launch_bounds__(256) k_compact(const int64_t* __restrict__ row
 
 __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int32_t* __restrict__ rlen, int32_t n,
                             int64_t m, long long max_subrounds, int sched, int fix_bits, int fix_vals, int pcap,
-                            unsigned long long* __restrict__ pslot) {
+                            unsigned long long* __restrict__ pslot, int first_level, int stop_level) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) rlen[i] = (int32_t)(row_ptr[i + 1] - row_ptr[i]);
   if (i < pcap) pslot[i] = 0ULL;
@@ -1001,7 +1003,7 @@ __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int
     c->w_work = 0ULL;
     c->w_fwork = 0ULL;
     c->phase = PH_SWEEP;
-    c->k = 1;
+    c->k = first_level - 1;  // the first sweep takes the frontier of level first_level
     c->r = 0;
     c->qlen = 0;
     c->acnt = (int)m;
@@ -1026,6 +1028,7 @@ __global__ void k_peel_init(PeelCtl* c, const int64_t* __restrict__ row_ptr, int
     c->sched = sched;
     c->fix_bits = fix_bits;
     c->fix_vals = fix_vals;
+    c->stop_level = stop_level;
     c->m_edges = (int)m;
     c->lvl_sub0 = 0;
     c->prev_sub = 0;
@@ -1080,7 +1083,8 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
   int64_t initn = dg.n > L.pcap ? dg.n : L.pcap;
   if (initn < 1) initn = 1;
   hipLaunchKernelGGL(k_peel_init, dim3((unsigned)((initn + 255) / 256)), dim3(256), 0, s, L.ctl, dg.row_ptr, L.rlen,
-                     dg.n, dg.m, maxsr, plan.sched, plan.fix_bits, plan.fix_vals, L.pcap, L.pslot);
+                     dg.n, dg.m, maxsr, plan.sched, plan.fix_bits, plan.fix_vals, L.pcap, L.pslot,
+                     plan.first_level < 2 ? 2 : plan.first_level, plan.stop_level);
   if (g_peel_blocks == 0) {
     int dev = 0, cus = 0, occ = 0;
     TRUSS_HIP(hipGetDevice(&dev));

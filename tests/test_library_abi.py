@@ -169,3 +169,26 @@ def test_core_and_cohesion_sizes_and_errors(T):
     st = T.CohesionStats()
     assert lib.truss_cohesion(ctypes.byref(g), None, None, 4096, 1 << 40, None) == T.E_INVAL
     assert lib.truss_cohesion(ctypes.byref(g), None, ctypes.byref(st), 4096, 16, None) == T.E_WORKSPACE
+
+
+def test_bottomup_sizes_and_errors(T):
+    lib = T.load_library()
+    assert ctypes.sizeof(T.BottomUpStats) == 128
+    b = ctypes.c_size_t(0)
+    assert lib.truss_bottomup_workspace_size(0, ctypes.byref(b)) == T.E_INVAL
+    assert lib.truss_bottomup_workspace_size(1000, ctypes.byref(b)) == 0 and b.value > 1000 * 17
+    small = b.value
+    assert lib.truss_bottomup_workspace_size(100000, ctypes.byref(b)) == 0 and b.value > small
+    import numpy as np
+    s = np.array([0, 2], np.int32)
+    d = np.array([1, 2], np.int32)
+    out = np.zeros(2, np.int32)
+    st = T.BottomUpStats()
+    # too small a workspace, then a self-loop found on the host before any device work
+    assert lib.truss_bottomup(4, 2, s.ctypes.data, d.ctypes.data, None, 10, out.ctypes.data, None, None,
+                              ctypes.byref(st), 4096, 16, None) == T.E_WORKSPACE
+    assert lib.truss_bottomup(4, 2, s.ctypes.data, d.ctypes.data, None, 10, out.ctypes.data, None, None,
+                              ctypes.byref(st), 4096, 1 << 40, None) == T.E_SELFLOOP
+    d2 = np.array([1, 4], np.int32)
+    assert lib.truss_bottomup(4, 2, s.ctypes.data, d2.ctypes.data, None, 10, out.ctypes.data, None, None,
+                              ctypes.byref(st), 4096, 1 << 40, None) == T.E_RANGE
