@@ -23,6 +23,8 @@
 // later passes go to G_new with their bound, and Algorithm 4 then starts at
 // k = 2.  Algorithm 4 skips each k for which no remaining edge has a bound
 // <= k (U_k and Phi_k are empty there).
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -47,9 +49,32 @@ struct HostGraph {
   int64_t m = 0;
   const int32_t* src = nullptr;
   const int32_t* dst = nullptr;
-  std::vector<int64_t> off;
+  std::vector<int64_t> off, end;  // row v holds entries off[v] .. end[v]
   std::vector<int32_t> nbr, eid;
+  int64_t stored = 0;             // entries held over all rows
+
+  // Keeps only the entries of edges with flag[e] == live once the live edges
+  // fill less than 70% of the entries held; rows keep their ascending order.
+  void compact(const uint8_t* flag, uint8_t live, int64_t live_edges) {
+    if (10 * (2 * live_edges) >= 7 * stored) return;
+    stored = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      int64_t w = off[v];
+      for (int64_t j = off[v]; j < end[v]; ++j)
+        if (flag[eid[(size_t)j]] == live) {
+          nbr[(size_t)w] = nbr[(size_t)j];
+          eid[(size_t)w++] = eid[(size_t)j];
+        }
+      end[v] = w;
+      stored += w - off[v];
+    }
+  }
 };
+
+bool verbose() {
+  const char* v = getenv("TRUSS_VERBOSE");
+  return v && *v && *v != '0';
+}
 
 int build_host_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, HostGraph& g) {
   g.n = n;
@@ -99,6 +124,8 @@ int build_host_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* ds
         set_last_error("edge (%d, %d) is given twice", v, g.nbr[(size_t)j]);
         return TRUSS_E_DUP;
       }
+  g.end.assign(g.off.begin() + 1, g.off.end());
+  g.stored = 2 * m;
   return TRUSS_OK;
 }
 
@@ -121,7 +148,7 @@ bool grow_parts(const HostGraph& g, const uint8_t* mask, const int64_t* w, int64
   for (int32_t r = 0; r < g.n; ++r) {
     if (P.part[r] >= 0) continue;
     bool has = false;
-    for (int64_t j = g.off[r]; j < g.off[(size_t)r + 1] && !has; ++j) has = mask[g.eid[(size_t)j]] != 0;
+    for (int64_t j = g.off[r]; j < g.end[r] && !has; ++j) has = mask[g.eid[(size_t)j]] != 0;
     if (!has) continue;
     if (w[r] > cap) {
       set_last_error("vertex %d alone needs %lld edges, more than the budget of %lld", r, (long long)w[r],
@@ -140,7 +167,7 @@ bool grow_parts(const HostGraph& g, const uint8_t* mask, const int64_t* w, int64
     P.order.push_back(r);
     while (head < P.order.size()) {
       const int32_t v = P.order[head++];
-      for (int64_t j = g.off[v]; j < g.off[(size_t)v + 1]; ++j) {
+      for (int64_t j = g.off[v]; j < g.end[v]; ++j) {
         const int32_t x = g.nbr[(size_t)j];
         if (!mask[g.eid[(size_t)j]] || P.part[x] >= 0 || sum + w[x] > cap) continue;
         P.part[x] = p;
@@ -253,7 +280,7 @@ int run_staged(const HostGraph& g, Device& D, const Staged& S, bool frozen, int 
 }
 
 struct Run {
-  const HostGraph& g;
+  HostGraph& g;
   Device& D;
   const truss_options* opts;
   hipStream_t s;
@@ -265,9 +292,10 @@ struct Run {
 // ---- LowerBounding (Algorithm 3) -------------------------------------------------
 int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, std::vector<uint8_t>& phi2) {
   const HostGraph& g = R.g;
+  const auto t0 = Clock::now();
   std::vector<uint8_t> alive((size_t)g.m, 1);
   std::vector<int64_t> deg((size_t)g.n);
-  for (int32_t v = 0; v < g.n; ++v) deg[v] = g.off[(size_t)v + 1] - g.off[v];
+  for (int32_t v = 0; v < g.n; ++v) deg[v] = g.end[v] - g.off[v];
   lb.assign((size_t)g.m, 2);  // Step 1 (the bound starts at 2, as in Example 3)
   phi2.assign((size_t)g.m, 0);
   Parts P;
@@ -306,7 +334,7 @@ int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, 
       S.flag.clear();
       for (int64_t i = P.start[(size_t)p]; i < P.start[(size_t)p + 1]; ++i) {
         const int32_t v = P.order[(size_t)i];
-        for (int64_t j = g.off[v]; j < g.off[(size_t)v + 1]; ++j) {
+        for (int64_t j = g.off[v]; j < g.end[v]; ++j) {
           const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
           if (!alive[(size_t)e]) continue;
           const bool inside = P.part[w] == p;
@@ -347,7 +375,10 @@ int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, 
                      (long long)R.cap);
       return TRUSS_E_WORKSPACE;
     }
-    left -= removed;
+    left -= removed;  // (rows are not compacted here: Algorithm 4 reads every edge of G_new from them)
+    if (verbose())
+      fprintf(stderr, "truss_bottomup: lower bounding pass %lld: %lld parts, %lld edges left, %.0f ms\n",
+              (long long)R.st.passes, (long long)P.count(), (long long)left, ms_since(t0));
   }
   return TRUSS_OK;
 }
@@ -421,7 +452,7 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& hi
         F.flag.clear();
         for (int64_t q = P.start[(size_t)p]; q < P.start[(size_t)p + 1]; ++q) {
           const int32_t v = P.order[(size_t)q];
-          for (int64_t j = g.off[v]; j < g.off[(size_t)v + 1]; ++j) {
+          for (int64_t j = g.off[v]; j < g.end[v]; ++j) {
             const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
             const int32_t i = hidx[(size_t)e];
             if (i < 0 || !inh[(size_t)i]) continue;
@@ -463,7 +494,8 @@ done:
 }
 
 int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>& phi2) {
-  const HostGraph& g = R.g;
+  HostGraph& g = R.g;
+  const auto t0 = Clock::now();
   BottomUp B{R, {}, {}, 0, 0};
   B.gone.assign((size_t)g.m, 0);
   B.cnt.assign((size_t)g.n, 0);
@@ -518,7 +550,7 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
     H.ids.clear();
     H.flag.clear();
     for (const int32_t u : ulist)
-      for (int64_t j = g.off[u]; j < g.off[(size_t)u + 1]; ++j) {
+      for (int64_t j = g.off[u]; j < g.end[u]; ++j) {
         const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
         if (B.gone[(size_t)e]) continue;
         const bool inside = B.cnt[w] > 0;
@@ -533,6 +565,11 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
                                                    : procedure9(B, H, k, hidx, &found);
     if (rc) return rc;
     if (found > 0) R.st.kmax = k;
+    if (verbose())
+      fprintf(stderr, "truss_bottomup: k %d: candidate of %zu edges (procedure %d), %lld in Phi_k, %lld left, %.0f ms\n",
+              k, H.ids.size(), (int64_t)H.ids.size() <= R.cap ? 5 : 9, (long long)found, (long long)B.left,
+              ms_since(t0));
+    g.compact(B.gone.data(), 0, B.left);
     k += 1;  // Step 8
   }
   return TRUSS_OK;
