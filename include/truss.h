@@ -230,6 +230,22 @@ int truss_topdown_workspace_size(const truss_graph *g, const truss_options *opts
 int truss_topdown(const truss_graph *g, int32_t t, int32_t *truss_out, int32_t *kmin_out, int32_t *kmax_out,
                   const truss_options *opts, truss_stats *stats, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Algorithm 1 (Section 3.1) as a comparator ------------------------------- */
+/* The decomposition of Algorithm 1 (Cohen): sup(e) = |nb(u) ∩ nb(v)| by
+ * merging the two full sorted rows (Steps 2-3); then for k = 3, 4, ... the
+ * edges with sup < k-2 leave, each finding its triangles by merging the two
+ * full rows again (Step 5; removed edges are only marked) and decrementing the
+ * two other edges of each (Steps 6-7).  truss_out (device) int32[m] as in
+ * "Output indexing" — the same truss numbers as truss_decompose.  stats
+ * (host, nullable): support_work and peel_work = row entries merged (for
+ * each edge deg(u) + deg(v) once in each stage, i.e. the sum over vertices of
+ * deg(v)^2 per stage), subrounds = frontier rounds, levels = non-empty
+ * levels.  Workspace from truss_cohen_workspace_size.  This entry point is
+ * the reference point of Algorithm 2's improvement (Table 3), not a fast path. */
+int truss_cohen_workspace_size(const truss_graph *g, size_t *bytes);
+int truss_cohen(const truss_graph *g, int32_t *truss_out, truss_stats *stats, void *ws, size_t ws_bytes,
+                void *stream);
+
 /* ---- k-cores and the cohesion comparison of Section 7 (Table 6) ---------- */
 /* Core numbers: the c-core is the largest subgraph whose vertices all have
  * degree >= c; core(v) is the largest c whose c-core holds v (0 for isolated

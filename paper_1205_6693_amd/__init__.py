@@ -150,6 +150,8 @@ def load_library():
     lib.truss_core_numbers.argtypes = [gp, vp, ctypes.POINTER(i32), vp, ctypes.c_size_t, vp]
     lib.truss_cohesion_workspace_size.argtypes = [gp, szp]
     lib.truss_cohesion.argtypes = [gp, op, ctypes.POINTER(CohesionStats), vp, ctypes.c_size_t, vp]
+    lib.truss_cohen_workspace_size.argtypes = [gp, szp]
+    lib.truss_cohen.argtypes = [gp, vp, sp, vp, ctypes.c_size_t, vp]
     lib.truss_bottomup_workspace_size.argtypes = [i64, szp]
     lib.truss_bottomup.argtypes = [i32, i64, vp, vp, vp, i64, vp, vp, op, ctypes.POINTER(BottomUpStats), vp,
                                    ctypes.c_size_t, vp]
@@ -168,7 +170,8 @@ def load_library():
               "truss_batch_plan_create", "truss_batch_plan_run", "truss_batch_autotune",
               "truss_upper_bound", "truss_topdown_workspace_size", "truss_topdown",
               "truss_core_workspace_size", "truss_core_numbers", "truss_cohesion_workspace_size",
-              "truss_cohesion", "truss_bottomup_workspace_size", "truss_bottomup",
+              "truss_cohesion", "truss_bottomup_workspace_size", "truss_bottomup", "truss_cohen_workspace_size",
+              "truss_cohen",
               "truss_mlp_param_count", "truss_mlp_workspace_size", "truss_mlp_forward",
               "truss_mlp_backward", "truss_mlp_train", "truss_sched_part_floats",
               "truss_sched_model_floats", "truss_sched_train_workspace_size", "truss_sched_train"):
@@ -602,3 +605,21 @@ def truss_bottomup(n: int, src, dst, cap: int, first_part=None, opts: Options | 
                               ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
                               _stream(stream)))
     return out[:m], low[:m], st.to_dict()
+
+
+def truss_cohen(graph: Graph, out=None, ws=None, stream=None):
+    """Algorithm 1 (Section 3.1) on the device: (truss numbers, stats).  The
+    comparator of Algorithm 2's improvement; the same truss numbers as
+    truss_decompose."""
+    torch = _torch()
+    lib = load_library()
+    if out is None:
+        out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    g = graph._c()
+    if ws is None:
+        b = ctypes.c_size_t(0)
+        _check(lib.truss_cohen_workspace_size(ctypes.byref(g), ctypes.byref(b)))
+        ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
+    st = Stats()
+    _check(lib.truss_cohen(ctypes.byref(g), _ptr(out), ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream)))
+    return out, st.to_dict()

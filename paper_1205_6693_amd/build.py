@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtruss.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["scan.hip", "build.hip", "support.hip", "peel.hip", "mlp.hip", "batch.hip", "bound.hip", "core.hip", "bottomup.hip", "api.hip"]
+SOURCES = ["scan.hip", "build.hip", "support.hip", "peel.hip", "mlp.hip", "batch.hip", "bound.hip", "core.hip", "bottomup.hip", "cohen.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

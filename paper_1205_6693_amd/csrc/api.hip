@@ -570,6 +570,62 @@ int run_topdown(const truss_graph* g, int32_t t, int32_t* out, int32_t* kmin_out
   return TRUSS_OK;
 }
 
+// ---- Algorithm 1 as a comparator ---------------------------------------------------
+size_t cohen_layout(const truss_graph* g, Arena& a) {
+  a.take<int>(64);
+  build_workspace(g, a);
+  a.take<int2>((size_t)g->m + 1);
+  a.take<int32_t>((size_t)g->m + 1);
+  cohen_workspace(g->m, a);
+  return a.used;
+}
+
+int run_cohen(const truss_graph* g, int32_t* out, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (g->m > 0 && !out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
+  Arena need;
+  need.counting = true;
+  const size_t bytes = cohen_layout(g, need);
+  if (!ws || ws_bytes < bytes) {
+    set_last_error("workspace of %zu bytes given, %zu needed", ws_bytes, bytes);
+    return TRUSS_E_WORKSPACE;
+  }
+  Arena a;
+  a.base = static_cast<char*>(ws);
+  a.cap = ws_bytes;
+  int* d_err = a.take<int>(64);
+  Timer tm(stats != nullptr, s);
+  tm.mark(0);
+  DevGraph dg;
+  if ((rc = build_graph(g, a, dg, d_err, s))) return rc;
+  tm.mark(1);
+  int2* sr = a.take<int2>((size_t)g->m + 1);
+  int32_t* tc = a.take<int32_t>((size_t)g->m + 1);
+  CohenResult cr;
+  if ((rc = cohen_decompose(dg, sr, g->fmt == TRUSS_FMT_EDGES ? tc : out, a, &cr, s))) return rc;
+  if (g->fmt == TRUSS_FMT_EDGES && g->m > 0)
+    hipLaunchKernelGGL(k_scatter_out, dim3(grid_for(g->m)), dim3(kT), 0, s, tc, dg.perm, g->m, out);
+  tm.mark(2);
+  TRUSS_HIP(hipGetLastError());
+  TRUSS_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->n = g->n;
+    stats->m = g->m;
+    stats->kmax = cr.kmax;
+    stats->levels = cr.levels;
+    stats->subrounds = cr.rounds;
+    stats->peel_work = cr.peel_work;
+    stats->support_work = cr.support_work;
+    stats->ms_build = tm.ms(0, 1);
+    stats->ms_support = cr.ms_support;
+    stats->ms_peel = cr.ms_peel;
+    stats->ms_total = tm.ms(0, 2);
+  }
+  return TRUSS_OK;
+}
+
 // ---- core numbers and the cohesion statistics of Table 6 ---------------------------
 size_t core_layout(const truss_graph* g, Arena& a) {
   a.take<int>(64);
@@ -891,6 +947,21 @@ int truss_topdown_workspace_size(const truss_graph* g, const truss_options* opts
 int truss_topdown(const truss_graph* g, int32_t t, int32_t* truss_out, int32_t* kmin_out, int32_t* kmax_out,
                   const truss_options* opts, truss_stats* stats, void* ws, size_t ws_bytes, void* stream) {
   return run_topdown(g, t, truss_out, kmin_out, kmax_out, opts, stats, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int truss_cohen_workspace_size(const truss_graph* g, size_t* bytes) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  if (!bytes) { set_last_error("bytes is NULL"); return TRUSS_E_INVAL; }
+  Arena a;
+  a.counting = true;
+  *bytes = cohen_layout(g, a);
+  return TRUSS_OK;
+}
+
+int truss_cohen(const truss_graph* g, int32_t* truss_out, truss_stats* stats, void* ws, size_t ws_bytes,
+                void* stream) {
+  return run_cohen(g, truss_out, stats, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int truss_core_workspace_size(const truss_graph* g, size_t* bytes) {

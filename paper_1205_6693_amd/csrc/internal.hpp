@@ -125,6 +125,16 @@ int compute_core_numbers(const DevGraph& dg, int32_t* core, int32_t* cmax_out, A
 int subgraph_vertex_stats(int32_t n, const int32_t* su, const int32_t* sv, const int32_t* sup, int64_t ms, Arena& a,
                           double* nv_out, double* cc_out, hipStream_t s);
 
+// Algorithm 1 (comparator): truss[e] for every canonical edge; sr is scratch
+// (support, removal round).  Workspace: cohen_workspace(m) after the build's.
+struct CohenResult {
+  int32_t kmax = 0, levels = 0;
+  int64_t rounds = 0, support_work = 0, peel_work = 0;  // work: row entries merged
+  double ms_support = 0, ms_peel = 0;
+};
+size_t cohen_workspace(int64_t m, Arena& a);
+int cohen_decompose(const DevGraph& dg, int2* sr, int32_t* truss, Arena& a, CohenResult* res, hipStream_t s);
+
 // One neighbourhood subgraph on the device, given as a device edge list of m
 // edges over vertices 0..n-1 (validated like truss_decompose's input).
 // Outputs are indexed like the edge list.  sup_out (nullable): sup(e) in the

@@ -192,3 +192,13 @@ def test_bottomup_sizes_and_errors(T):
     d2 = np.array([1, 4], np.int32)
     assert lib.truss_bottomup(4, 2, s.ctypes.data, d2.ctypes.data, None, 10, out.ctypes.data, None, None,
                               ctypes.byref(st), 4096, 1 << 40, None) == T.E_RANGE
+
+
+def test_cohen_workspace(T):
+    lib = T.load_library()
+    b = ctypes.c_size_t(0)
+    assert lib.truss_cohen_workspace_size(ctypes.byref(_graph(T, 1000, 5000)), ctypes.byref(b)) == 0
+    assert b.value > 5000 * 16
+    assert lib.truss_cohen_workspace_size(None, ctypes.byref(b)) == T.E_INVAL
+    g = _graph(T, 1000, 5000)
+    assert lib.truss_cohen(ctypes.byref(g), 4096, None, 4096, 16, None) == T.E_WORKSPACE
