@@ -265,6 +265,11 @@ def main():
     ap.add_argument("--bottomup", type=float, default=0.0, metavar="FRACTION",
                     help="also run the bottom-up decomposition from host memory with a device budget of "
                          "FRACTION * m edges per subgraph")
+    ap.add_argument("--cohen", action="store_true",
+                    help="also time Algorithm 1 (the comparator of Table 3) on the workload")
+    ap.add_argument("--cohen-sweep", action="store_true",
+                    help="Table 3's shape: Algorithm 1 against the learned Algorithm 2 path on Chung-Lu graphs "
+                         "of growing maximum degree")
     ap.add_argument("--cohesion", action="store_true",
                     help="also time the core numbers and the cohesion statistics of Table 6")
     ap.add_argument("--batch-shape", type=int, nargs=2, default=None, metavar=("THREADS", "ILP"),
@@ -433,6 +438,10 @@ def main():
         result["cohesion"] = time_cohesion(T, torch, g, opts, args)
     if args.bottomup > 0:
         result["bottomup"] = time_bottomup(T, n, host_edges[0], host_edges[1], opts, out, args)
+    if args.cohen:
+        result["cohen"] = time_cohen(T, torch, g, out, ms_per_step, args)
+    if args.cohen_sweep:
+        result["cohen_sweep"] = cohen_sweep(T, torch, opts)
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale, args.seed)
@@ -453,6 +462,60 @@ def time_bottomup(T, n, s, d, opts, out, args):
              st["candidates"], st["proc9_calls"], st["proc9_scans"], st["device_calls"], st["bytes_h2d"] / 1e9,
              same), file=sys.stderr, flush=True)
     return dict(st, budget_edges=cap, equal_to_in_memory=same)
+
+
+def time_cohen(T, torch, g, out, ms_alg2, args):
+    """Algorithm 1 on the workload graph, checked against the output just timed."""
+    reps = max(1, min(args.steps, 3))
+    res, st = T.truss_cohen(g)
+    same = bool(torch.equal(res, out))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        res, st = T.truss_cohen(g)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / reps
+    print("algorithm 1: %.1f ms (support %.1f, peel %.1f), %.3g row entries merged; algorithm 2 path %.1f ms "
+          "(%.1fx); equal: %s" % (ms, st["ms_support"], st["ms_peel"], st["support_work"] + st["peel_work"],
+                                  ms_alg2, ms / ms_alg2, same), file=sys.stderr, flush=True)
+    return {"ms_per_call": ms, "ms_support": st["ms_support"], "ms_peel": st["ms_peel"],
+            "entries_merged": st["support_work"] + st["peel_work"], "alg2_ms": ms_alg2,
+            "alg1_over_alg2": ms / ms_alg2, "equal": same}
+
+
+def cohen_sweep(T, torch, opts):
+    """Chung-Lu graphs, n = 2^18, mean degree 30, weight cap 10^5, no cliques,
+    seed 7, with the power-law exponent falling from 3.5 to 2.1 (so the degree
+    skew and the largest degree grow, at about 3.3-3.9 M edges): the time of
+    Algorithm 1 over that of the Algorithm 2 path (Table 3 reports 2.2x to
+    73.2x on four real graphs, growing with the largest degree)."""
+    import graphgen
+    rows = []
+    for gamma in (3.5, 3.0, 2.6, 2.3, 2.1):
+        n, s, d = graphgen.chung_lu(1 << 18, gamma, 30.0, 100000.0, 0, 0, 0, 7)
+        row_ptr, col = graphgen.to_csr(n, s, d)
+        g = T.Graph.from_csr(n, torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda())
+        deg = np.diff(row_ptr)
+        times = {}
+        for name, fn in (("alg2", lambda: T.truss_decompose(g, opts)), ("alg1", lambda: T.truss_cohen(g))):
+            fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(3):
+                o, st = fn()
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t1) * 1e3 / 3
+            times[name + "_out"] = o
+        same = bool(torch.equal(times.pop("alg1_out"), times.pop("alg2_out")))
+        row = {"exponent": gamma, "m": int(s.size), "d_max": int(deg.max()),
+               "sum_deg2_over_m": float((deg.astype(np.float64) ** 2).sum() / max(1, s.size)),
+               "alg1_ms": times["alg1"], "alg2_ms": times["alg2"], "speedup": times["alg1"] / times["alg2"],
+               "equal": same}
+        print("sweep: d_max %d, sum deg^2/m %.0f: algorithm 1 %.1f ms, algorithm 2 path %.1f ms, %.1fx, equal %s"
+              % (row["d_max"], row["sum_deg2_over_m"], row["alg1_ms"], row["alg2_ms"], row["speedup"], same),
+              file=sys.stderr, flush=True)
+        rows.append(row)
+    return rows
 
 
 def time_cohesion(T, torch, g, opts, args):
