@@ -137,10 +137,24 @@ struct Parts {
   int64_t count() const { return (int64_t)start.size() - 1; }
 };
 
-// Parts grown breadth-first (see the file comment).  mask: by edge id, the
+// Rows of a graph: vertex v's entries (neighbour, edge index) are
+// off[v] .. end[v], ascending by neighbour.
+struct Rows {
+  int32_t n;
+  const int64_t* off;
+  const int64_t* end;
+  const int32_t* nbr;
+  const int32_t* eid;
+};
+
+Rows rows_of(const HostGraph& g) {
+  return Rows{g.n, g.off.data(), g.end.data(), g.nbr.data(), g.eid.data()};
+}
+
+// Parts grown breadth-first (see the file comment).  mask: by edge index, the
 // edges of the graph being partitioned.  Returns false if a vertex alone
 // weighs more than cap.
-bool grow_parts(const HostGraph& g, const uint8_t* mask, const int64_t* w, int64_t cap, Parts& P) {
+bool grow_parts(const Rows& g, const uint8_t* mask, const int64_t* w, int64_t cap, Parts& P) {
   P.part.assign((size_t)g.n, -1);
   P.order.clear();
   P.start.assign(1, 0);
@@ -148,7 +162,7 @@ bool grow_parts(const HostGraph& g, const uint8_t* mask, const int64_t* w, int64
   for (int32_t r = 0; r < g.n; ++r) {
     if (P.part[r] >= 0) continue;
     bool has = false;
-    for (int64_t j = g.off[r]; j < g.end[r] && !has; ++j) has = mask[g.eid[(size_t)j]] != 0;
+    for (int64_t j = g.off[r]; j < g.end[r] && !has; ++j) has = mask[g.eid[j]] != 0;
     if (!has) continue;
     if (w[r] > cap) {
       set_last_error("vertex %d alone needs %lld edges, more than the budget of %lld", r, (long long)w[r],
@@ -168,8 +182,8 @@ bool grow_parts(const HostGraph& g, const uint8_t* mask, const int64_t* w, int64
     while (head < P.order.size()) {
       const int32_t v = P.order[head++];
       for (int64_t j = g.off[v]; j < g.end[v]; ++j) {
-        const int32_t x = g.nbr[(size_t)j];
-        if (!mask[g.eid[(size_t)j]] || P.part[x] >= 0 || sum + w[x] > cap) continue;
+        const int32_t x = g.nbr[j];
+        if (!mask[g.eid[j]] || P.part[x] >= 0 || sum + w[x] > cap) continue;
         P.part[x] = p;
         sum += w[x];
         P.order.push_back(x);
@@ -324,7 +338,7 @@ int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, 
       P.order.assign((size_t)cnt[(size_t)parts], 0);
       for (int32_t v = 0; v < g.n; ++v)
         if (P.part[v] >= 0) P.order[(size_t)cnt[P.part[v]]++] = v;
-    } else if (!grow_parts(g, alive.data(), deg.data(), R.cap, P)) {  // Step 3
+    } else if (!grow_parts(rows_of(g), alive.data(), deg.data(), R.cap, P)) {  // Step 3
       return TRUSS_E_WORKSPACE;
     }
     int64_t removed = 0;
@@ -412,18 +426,78 @@ int procedure5(BottomUp& B, const Staged& H, int32_t k, int64_t* found) {
   return TRUSS_OK;
 }
 
+// The candidate subgraph H as rows of its own: local vertex ids in ascending
+// global id (so the partition visits vertices and neighbours in the same order
+// as on the whole graph), edge indices into H.
+struct LocalRows {
+  std::vector<int32_t> gid;  // local vertex -> global vertex
+  std::vector<int64_t> off, end;
+  std::vector<int32_t> nbr, eid;
+  std::vector<int32_t> lu, lv;  // local endpoints of H's edges
+  Rows view() const {
+    return Rows{(int32_t)gid.size(), off.data(), end.data(), nbr.data(), eid.data()};
+  }
+};
+
+void build_local_rows(const HostGraph& g, const Staged& H, std::vector<int32_t>& lid, LocalRows& L) {
+  const size_t h = H.ids.size();
+  L.gid.clear();
+  for (size_t i = 0; i < h; ++i)
+    for (const int32_t v : {g.src[H.ids[i]], g.dst[H.ids[i]]})
+      if (lid[v] < 0) {
+        lid[v] = 0;
+        L.gid.push_back(v);
+      }
+  std::sort(L.gid.begin(), L.gid.end());
+  const int32_t nl = (int32_t)L.gid.size();
+  for (int32_t x = 0; x < nl; ++x) lid[L.gid[x]] = x;
+  L.lu.resize(h);
+  L.lv.resize(h);
+  L.off.assign((size_t)nl + 1, 0);
+  for (size_t i = 0; i < h; ++i) {
+    L.lu[i] = lid[g.src[H.ids[i]]];
+    L.lv[i] = lid[g.dst[H.ids[i]]];
+    L.off[(size_t)L.lu[i] + 1]++;
+    L.off[(size_t)L.lv[i] + 1]++;
+  }
+  for (int32_t x = 0; x < nl; ++x) L.off[(size_t)x + 1] += L.off[x];
+  for (const int32_t v : L.gid) lid[v] = -1;
+  // rows in edge order, then transposed so each row is ascending
+  std::vector<int32_t> tn(2 * h), te(2 * h);
+  std::vector<int64_t> fill(L.off.begin(), L.off.end() - 1);
+  for (size_t i = 0; i < h; ++i) {
+    tn[(size_t)fill[L.lu[i]]] = L.lv[i];
+    te[(size_t)fill[L.lu[i]]++] = (int32_t)i;
+    tn[(size_t)fill[L.lv[i]]] = L.lu[i];
+    te[(size_t)fill[L.lv[i]]++] = (int32_t)i;
+  }
+  L.nbr.resize(2 * h);
+  L.eid.resize(2 * h);
+  std::copy(L.off.begin(), L.off.end() - 1, fill.begin());
+  for (int32_t x = 0; x < nl; ++x)
+    for (int64_t j = L.off[x]; j < L.off[(size_t)x + 1]; ++j) {
+      const int32_t y = tn[(size_t)j];
+      L.nbr[(size_t)fill[y]] = x;
+      L.eid[(size_t)fill[y]++] = te[(size_t)j];
+    }
+  L.end.assign(L.off.begin() + 1, L.off.end());
+}
+
 // Procedure 9: H exceeds the budget; its internal edges are examined part by
 // part until a whole scan adds nothing to Phi_k.
-int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& hidx, int64_t* found_total) {
+int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& lid, int64_t* found_total) {
   Run& R = B.R;
   const HostGraph& g = R.g;
   const size_t h = H.ids.size();
-  std::vector<uint8_t> inh(h, 1), cov(h, 0), mask((size_t)g.m, 0);
-  std::vector<int64_t> deg((size_t)g.n, 0);
-  for (size_t i = 0; i < h; ++i) hidx[(size_t)H.ids[i]] = (int32_t)i;
+  LocalRows L;
+  build_local_rows(g, H, lid, L);
+  const Rows rows = L.view();
+  std::vector<uint8_t> inh(h, 1), cov(h, 0), mask(h, 0);
+  std::vector<int64_t> deg((size_t)rows.n, 0);
+  std::vector<int32_t> fidx;
+  std::vector<uint8_t> fin;
   Parts P;
   Staged F;
-  int rc = TRUSS_OK;
   R.st.proc9_calls += 1;
   for (;;) {  // Steps 2-14
     int64_t found = 0;
@@ -432,65 +506,60 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& hi
       int64_t left = 0;
       std::fill(deg.begin(), deg.end(), 0);
       for (size_t i = 0; i < h; ++i) {
-        const int32_t e = H.ids[i];
-        mask[(size_t)e] = inh[i] && !cov[i];
+        mask[i] = inh[i] && !cov[i];
         if (!inh[i]) continue;
-        deg[g.src[e]] += 1;
-        deg[g.dst[e]] += 1;
+        deg[(size_t)L.lu[i]] += 1;
+        deg[(size_t)L.lv[i]] += 1;
         left += !cov[i];
       }
       if (left == 0) break;
       R.st.proc9_scans += 1;
-      if (!grow_parts(g, mask.data(), deg.data(), R.cap, P)) {  // Step 4
-        rc = TRUSS_E_WORKSPACE;
-        goto done;
-      }
+      if (!grow_parts(rows, mask.data(), deg.data(), R.cap, P)) return TRUSS_E_WORKSPACE;  // Step 4
       int64_t covered = 0;
       for (int64_t p = 0; p < P.count(); ++p) {  // Step 5
         // Step 6: F = NS(P_p) in the current H; flag = eligible (internal to F and to H)
         F.ids.clear();
         F.flag.clear();
+        fidx.clear();
+        fin.clear();
         for (int64_t q = P.start[(size_t)p]; q < P.start[(size_t)p + 1]; ++q) {
           const int32_t v = P.order[(size_t)q];
-          for (int64_t j = g.off[v]; j < g.end[v]; ++j) {
-            const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
-            const int32_t i = hidx[(size_t)e];
-            if (i < 0 || !inh[(size_t)i]) continue;
+          for (int64_t j = rows.off[v]; j < rows.end[v]; ++j) {
+            const int32_t i = rows.eid[j], w = rows.nbr[j];
+            if (!inh[(size_t)i]) continue;
             const bool inside = P.part[w] == p;
             if (inside && w < v) continue;
-            F.ids.push_back(e);
+            F.ids.push_back(H.ids[(size_t)i]);
             F.flag.push_back(inside && H.flag[(size_t)i] ? 1 : 0);
+            fidx.push_back(i);
+            fin.push_back(inside ? 1 : 0);
           }
         }
         if (F.ids.empty()) continue;
-        rc = run_staged(g, R.D, F, true, k, k, false, R.opts, R.s);  // Steps 7-11
-        if (rc) goto done;
+        const int rc = run_staged(g, R.D, F, true, k, k, false, R.opts, R.s);  // Steps 7-11
+        if (rc) return rc;
         for (size_t j = 0; j < F.ids.size(); ++j) {
-          const int32_t e = F.ids[j];
-          const int32_t i = hidx[(size_t)e];
+          const size_t i = (size_t)fidx[j];
           if (F.flag[j] && R.D.h_out[j] == k) {  // Step 12
-            B.output(e, k);
-            inh[(size_t)i] = 0;
+            B.output(F.ids[j], k);
+            inh[i] = 0;
             found += 1;
           }
-          if (P.part[g.src[e]] == p && P.part[g.dst[e]] == p && !cov[(size_t)i]) {  // Step 13
-            cov[(size_t)i] = 1;
+          if (fin[j] && !cov[i]) {  // Step 13
+            cov[i] = 1;
             covered += 1;
           }
         }
       }
       if (covered == 0) {
         set_last_error("procedure 9 made no progress: the budget of %lld edges is too small", (long long)R.cap);
-        rc = TRUSS_E_WORKSPACE;
-        goto done;
+        return TRUSS_E_WORKSPACE;
       }
     }
     *found_total += found;
     if (found == 0) break;  // Step 14
   }
-done:
-  for (size_t i = 0; i < h; ++i) hidx[(size_t)H.ids[i]] = -1;
-  return rc;
+  return TRUSS_OK;
 }
 
 int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>& phi2) {
@@ -518,7 +587,7 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
   std::vector<int32_t> sorted((size_t)B.left);
   for (int64_t e = 0; e < g.m; ++e)
     if (!phi2[(size_t)e]) sorted[(size_t)byb[lb[(size_t)e]]++] = (int32_t)e;
-  std::vector<int32_t> ulist, hidx((size_t)g.m, -1);
+  std::vector<int32_t> ulist, lid((size_t)g.n, -1);
   std::vector<uint8_t> inlist((size_t)g.n, 0);
   size_t ap = 0;
   Staged H;
@@ -562,7 +631,7 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
     R.st.max_candidate = std::max(R.st.max_candidate, (int64_t)H.ids.size());
     int64_t found = 0;
     const int rc = (int64_t)H.ids.size() <= R.cap ? procedure5(B, H, k, &found)  // Step 6
-                                                   : procedure9(B, H, k, hidx, &found);
+                                                   : procedure9(B, H, k, lid, &found);
     if (rc) return rc;
     if (found > 0) R.st.kmax = k;
     if (verbose())
