@@ -22,6 +22,7 @@ WORKLOADS = {
     "rmat16": lambda: graphgen.rmat(16, 16, 1),
     "rmat20": lambda: graphgen.rmat20(1),
     "chunglu4m": lambda: graphgen.chung_lu4m(1),
+    "rmat24": lambda: graphgen.rmat24(1),  # 260M edges: about a minute of host-side generation
 }
 
 # scheduler 0 = plain (merge support, dense frontier, bsearch probes),
