@@ -52,15 +52,49 @@ def make_graph(name: str, seed: int):
 
 
 def host_work_model(n, row_ptr, col):
-    """Per-unit counts of the algorithmic byte model: oriented (b, c) pairs the
-    support kernels examine, and the oriented edge count."""
-    deg = np.diff(row_ptr)
+    """Unit counts of the algorithmic byte models, from the graph itself:
+    oriented (b, c) pairs and edges (support as walked), sum over oriented
+    edges of d+(a) + d+(b) (the merge-form reference count of support), and
+    over the edges of min(deg u, deg v) and min(deg) * ceil(log2 max(deg)) (the
+    walk of the smaller endpoint's full row and its binary-search probes in
+    Algorithm 2)."""
+    deg = np.diff(row_ptr).astype(np.int64)
     rows = np.repeat(np.arange(n, dtype=np.int64), deg)
     c = col.astype(np.int64)
     before = (deg[rows] < deg[c]) | ((deg[rows] == deg[c]) & (rows < c))
     dplus = np.bincount(rows[before], minlength=n).astype(np.int64)
     pairs = int(dplus[c[before]].sum())  # sum over a->b of d+(b)
-    return {"support_pairs": pairs, "oriented_edges": int(before.sum()), "max_outdeg": int(dplus.max(initial=0))}
+    upper = rows < c  # every undirected edge once
+    du, dv = deg[rows[upper]], deg[c[upper]]
+    mn, mx = np.minimum(du, dv), np.maximum(du, dv)
+    lg = np.ceil(np.log2(np.maximum(mx, 1).astype(np.float64))).astype(np.int64)
+    return {"support_pairs": pairs, "oriented_edges": int(before.sum()), "max_outdeg": int(dplus.max(initial=0)),
+            "merge_elems": int((dplus * dplus).sum()) + pairs, "sum_min_deg": int(mn.sum()),
+            "sum_min_deg_log": int((mn * lg).sum())}
+
+
+def edge_work_model(n, s, d):
+    """host_work_model's counts from an edge list (each undirected edge once)."""
+    s = s.astype(np.int64)
+    d = d.astype(np.int64)
+    deg = np.bincount(np.concatenate([s, d]), minlength=n).astype(np.int64)
+    fwd = (deg[s] < deg[d]) | ((deg[s] == deg[d]) & (s < d))
+    a = np.where(fwd, s, d)
+    b = np.where(fwd, d, s)
+    dplus = np.bincount(a, minlength=n).astype(np.int64)
+    mn = np.minimum(deg[s], deg[d])
+    mx = np.maximum(deg[s], deg[d])
+    lg = np.ceil(np.log2(np.maximum(mx, 1).astype(np.float64))).astype(np.int64)
+    return {"support_pairs": int(dplus[b].sum()), "oriented_edges": int(s.size),
+            "merge_elems": int((dplus[a] + dplus[b]).sum()), "sum_min_deg": int(mn.sum()),
+            "sum_min_deg_log": int((mn * lg).sum())}
+
+
+def method_bytes(model, m, triangles):
+    """Algorithmic bytes of support and peeling for the method (see main)."""
+    sup = 4 * model["merge_elems"] + 16 * triangles + 20 * m
+    peel = 16 * m + 8 * model["sum_min_deg"] + 4 * model["sum_min_deg_log"] + 8 * triangles + 4 * m + 8 * m
+    return sup, peel
 
 
 def source_digest():
@@ -184,10 +218,20 @@ def bench_batch(args):
     ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
     st = stats[-1]
     kms = float(np.mean([x["ms_peel_kernel"] for x in stats]))
-    # algorithmic bytes of the batch kernel, per unit (documented in the design doc):
-    # 56 B per edge (input, canonical pair, CSR build and sort, output),
-    # 8 B per support walk entry, 16 B per peeling walk entry
-    alg = 56 * m + 8 * st["support_work"] + 16 * st["peel_work"]
+    # algorithmic bytes of the batch kernel: the method's support and peeling
+    # bytes of every graph (the per-unit figures of the single-graph bench)
+    # plus 56 B per edge for the per-graph build (input, canonical pair, CSR
+    # build and sort, output); beside them the bytes as walked here: 56 B per
+    # edge, 8 B per support walk entry, 16 B per peeling walk entry
+    alg = 56 * m
+    for g in range(4096):
+        ng = int(vo[g + 1] - vo[g])
+        sg, dg = s[eo[g]:eo[g + 1]], d[eo[g]:eo[g + 1]]
+        if sg.size:
+            mdl = edge_work_model(ng, sg, dg)
+            alg += sum(method_bytes(mdl, int(sg.size), 0))
+    alg += 24 * st["triangles"]  # the triangle terms of both stages (16 + 8 B per triangle)
+    walked = 56 * m + 8 * st["support_work"] + 16 * st["peel_work"]
     achieved = alg / (kms * 1e-3) / 1e9
     per_graph = None
     if not args.no_compare:
@@ -222,7 +266,10 @@ def bench_batch(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": measured_traffic("batch4096", "k_batch", 1), "kernel": "k_batch",
-                     "launches_per_step": 1, "avg_launch_ms": round(kms, 4), "bytes_per_launch": int(alg)},
+                     "launches_per_step": 1, "avg_launch_ms": round(kms, 4), "bytes_per_launch": int(alg),
+                     "achieved_walked": round(walked / (kms * 1e-3) / 1e9, 2),
+                     "frac_walked": round(walked / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                     "walked_bytes_per_launch": int(walked)},
         "per_graph_launches": per_graph,
     }
     if per_graph:
@@ -361,21 +408,33 @@ def main():
     ms_peel_kernel = avg("ms_peel_kernel")
     st = stats[-1]
     launches = max(1, st["launches"])
-    # algorithmic bytes (per-unit figures are documented in the design doc)
-    sup_bytes = 4 * model["support_pairs"] + 24 * model["oriented_edges"] + 8 * st["triangles"]
-    peel_bytes = 16 * st["peel_work"] + 44 * m
+    # algorithmic bytes: the per-unit figures of the byte model for the method
+    # (support, merge form: 4 B per list element compared, 16 B per triangle,
+    # 20 B per edge; peeling: per edge 16 B + 8 B per entry of the smaller
+    # endpoint's row + 4 B per binary-search step of its probes, 8 B per
+    # triangle, 4 B truss and 8 B of frontier per edge), and beside them the
+    # bytes of what the kernels walk here (after row compaction, hash probes)
+    T3 = st["triangles"]
+    sup_bytes, peel_bytes = method_bytes(model, m, T3)
+    sup_walked = 4 * model["support_pairs"] + 24 * model["oriented_edges"] + 8 * T3
+    peel_walked = 16 * st["peel_work"] + 44 * m
     kernels = {
-        "support": {"bytes": sup_bytes, "ms": ms_sup, "launches": 1, "name": "support kernels"},
-        "peel": {"bytes": peel_bytes, "ms": ms_peel_kernel, "launches": launches, "name": "k_peel"},
+        "support": {"bytes": sup_bytes, "walked": sup_walked, "ms": ms_sup, "launches": 1,
+                    "name": "support kernels"},
+        "peel": {"bytes": peel_bytes, "walked": peel_walked, "ms": ms_peel_kernel, "launches": launches,
+                 "name": "k_peel"},
     }
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9
+    walked = kd["walked"] / (kd["ms"] * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, kd["name"], kd["launches"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kd["name"],
                 "launches_per_step": kd["launches"], "avg_launch_ms": round(kd["ms"] / kd["launches"], 4),
-                "bytes_per_launch": int(kd["bytes"] / kd["launches"])}
+                "bytes_per_launch": int(kd["bytes"] / kd["launches"]),
+                "achieved_walked": round(walked, 2), "frac_walked": round(walked / HBM_PEAK_GBS, 5),
+                "walked_bytes_per_launch": int(kd["walked"] / kd["launches"])}
     result = {
         "metric": "truss-decomposed edges/s + HBM GB/s, plain vs learned-scheduled, 1 MI355X",
         "value": m / (ms_per_step * 1e-3), "unit": "edges/s",
@@ -392,7 +451,8 @@ def main():
         "peel_phase_ms": dict(zip(["sweep", "start", "rounds", "pieces", "dense"], st["ms_phase"][:5])),
         "roofline": roofline,
         "roofline_all": {k: {"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2), "ms": round(v["ms"], 3),
-                             "bytes": v["bytes"]} for k, v in kernels.items()},
+                             "bytes": v["bytes"], "walked_GB/s": round(v["walked"] / (v["ms"] * 1e-3) / 1e9, 2),
+                             "walked_bytes": v["walked"]} for k, v in kernels.items()},
         "peel_kernel_ms": ms_peel_kernel,
     }
     forms = {args.scheduler: {"edges_per_s": result["value"], "ms_per_step": ms_per_step}}
