@@ -51,7 +51,11 @@ namespace {
 
 constexpr int kT = 1024;
 constexpr int kWaves = kT / kWave;
-constexpr int kSeg = 4 * 1024;  // adjacency entries per segment of a chunk's walks (kNI per thread)
+// adjacency entries per segment of a chunk's walks: smaller segments spread
+// mid-size rounds over more workgroups, larger ones cut the announcement
+// traffic of rounds with big frontiers
+constexpr int kSegSmall = 2 * 1024, kSegLarge = 4 * 1024;
+constexpr int kSegLargeFrontier = 8192;  // frontiers of at least this many edges use kSegLarge
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kHistBins = 6;
 constexpr long long kCompactNum = 7, kCompactDen = 10;  // row compaction threshold
@@ -802,10 +806,11 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       // chunk of every workgroup is static, the rest are fetched).  Small
       // frontiers are spread over all workgroups (cs ~ |F| / workgroups, at
       // least 64).  The walks of a chunk are laid end to end and cut into
-      // segments of kSeg entries; the workgroup walks segment 0 and announces
+      // segments of seg entries; the workgroup walks segment 0 and announces
       // the others for any workgroup to take.  A segment is announced by one
       // 64-bit store into a slot.
       const int cs = chunk_size(qn, (int)gridDim.x);
+      const int seg = qn >= kSegLargeFrontier ? kSegLarge : kSegSmall;
       bool first_chunk = true;
       for (;;) {
         if (tid == 0) s_c0 = first_chunk ? (int)blockIdx.x * cs : (int)gridDim.x * cs + atomicAdd(&c->w_fetch, cs);
@@ -833,7 +838,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         s_e[tid] = e;
         s_b[tid] = b;
         s_base[tid] = ra;
-        const int nseg = (W + kSeg - 1) / kSeg;
+        const int nseg = (W + seg - 1) / seg;
         int npub = 0;  // segments 1..npub are announced
         if (nseg > 1) {
           // chunk tables for other workgroups, then the segment announcements
@@ -856,9 +861,9 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
             stc(&slots[pbase + (unsigned long long)(sg - 1)], code0 | (unsigned)sg);
         }
         __syncthreads();
-        walk(0, W < kSeg ? W : kSeg);
+        walk(0, W < seg ? W : seg);
         // segments that found no slot
-        for (int sg = npub + 1; sg < nseg; ++sg) walk(sg * kSeg, (sg + 1) * kSeg < W ? (sg + 1) * kSeg : W);
+        for (int sg = npub + 1; sg < nseg; ++sg) walk(sg * seg, (sg + 1) * seg < W ? (sg + 1) * seg : W);
         if (tid == 0) atomicAdd(&c->w_chunks, 1);
         __syncthreads();
       }
@@ -937,7 +942,7 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
         const int W = ldc(&P.rec_tot[c0 / cs]);
         if (tid == 0) s_pre[kT] = W;
         __syncthreads();
-        walk(sg * kSeg, (sg + 1) * kSeg < W ? (sg + 1) * kSeg : W);
+        walk(sg * seg, (sg + 1) * seg < W ? (sg + 1) * seg : W);
         __syncthreads();
       }
       wq_flush(wq);
