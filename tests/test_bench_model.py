@@ -1,0 +1,78 @@
+"""CPU checks of the benchmark's host logic: the unit counts of its byte
+models agree between the CSR and edge-list forms and with their definitions
+on small graphs, the merge-form support count equals the sum over edges of
+the smaller degree, the recorded-traffic lookup refuses a summary taken on
+other sources, and --gpus N > 1 stops before touching a GPU."""
+import itertools
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import graphgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _brute_counts(n, s, d):
+    deg = np.bincount(np.concatenate([s, d]), minlength=n)
+    before = lambda a, b: (deg[a], a) < (deg[b], b)  # noqa: E731
+    out = {a: set() for a in range(n)}
+    for a, b in zip(s.tolist(), d.tolist()):
+        if before(a, b):
+            out[a].add(b)
+        else:
+            out[b].add(a)
+    pairs = sum(len(out[b]) for a in range(n) for b in out[a])
+    merge = sum(len(out[a]) + len(out[b]) for a in range(n) for b in out[a])
+    mn = sum(min(deg[a], deg[b]) for a, b in zip(s, d))
+    lg = sum(min(deg[a], deg[b]) * int(np.ceil(np.log2(max(deg[a], deg[b], 1)))) for a, b in zip(s, d))
+    return {"support_pairs": pairs, "merge_elems": merge, "sum_min_deg": mn, "sum_min_deg_log": lg}
+
+
+def test_models_match_definitions():
+    rng = np.random.default_rng(4)
+    for trial in range(10):
+        n = int(rng.integers(5, 40))
+        pairs = [(a, b) for a, b in itertools.combinations(range(n), 2) if rng.random() < 0.3]
+        if not pairs:
+            continue
+        s, d = np.array(pairs, np.int32).T.copy()
+        ref = _brute_counts(n, s, d)
+        e = bench.edge_work_model(n, s, d)
+        rp, col = graphgen.to_csr(n, s, d)
+        c = bench.host_work_model(n, rp, col)
+        for k, v in ref.items():
+            assert e[k] == v and c[k] == v, (k, e[k], c[k], v)
+        assert e["merge_elems"] == e["sum_min_deg"]  # each oriented a->b: min degree = d+(a) + d-(a)
+
+
+def test_models_agree_on_rmat():
+    n, s, d = graphgen.rmat(12, 8, 3)
+    rp, col = graphgen.to_csr(n, s, d)
+    c = bench.host_work_model(n, rp, col)
+    e = bench.edge_work_model(n, s, d)
+    for k in ("support_pairs", "oriented_edges", "merge_elems", "sum_min_deg", "sum_min_deg_log"):
+        assert c[k] == e[k], k
+    sup, peel = bench.method_bytes(e, s.size, 1000)
+    assert sup == 4 * e["merge_elems"] + 16 * 1000 + 20 * s.size
+    assert peel == 28 * s.size + 8 * e["sum_min_deg"] + 4 * e["sum_min_deg_log"] + 8 * 1000
+
+
+def test_traffic_lookup_needs_matching_sources(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    f = tmp_path / "traffic_k_peel_demo.txt"
+    f.write_text("hbm_bytes_per_launch: 1.5e+09\nsource_digest: 0000000000000000\n")
+    assert bench.measured_traffic("demo", "k_peel", 1) is None
+    f.write_text("hbm_bytes_per_launch: 1.5e+09\nsource_digest: %s\n" % bench.source_digest())
+    assert bench.measured_traffic("demo", "k_peel", 1) == 1500000000
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, env=dict(os.environ, HIP_VISIBLE_DEVICES=""))
+    assert r.returncode != 0
+    assert "--gpus 1" in r.stderr
