@@ -202,3 +202,13 @@ def test_cohen_workspace(T):
     assert lib.truss_cohen_workspace_size(None, ctypes.byref(b)) == T.E_INVAL
     g = _graph(T, 1000, 5000)
     assert lib.truss_cohen(ctypes.byref(g), 4096, None, 4096, 16, None) == T.E_WORKSPACE
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No CPU fallback: without the built library the binding raises."""
+    import subprocess
+    import sys
+    code = ("import paper_1205_6693_amd as T; T.LIB_PATH = %r\n"
+            "try:\n    T.load_library()\nexcept ImportError as e:\n    print('raised', e)\n" % str(tmp_path / "none.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert "raised" in r.stdout and "not built" in r.stdout, r.stdout + r.stderr
