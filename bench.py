@@ -97,15 +97,24 @@ def method_bytes(model, m, triangles):
     return sup, peel
 
 
-def source_digest():
-    """Digest of the kernel sources; recorded traffic is valid only for the same sources."""
+# sources that decide what a profiled kernel does on the benchmark's input: its
+# own translation unit and headers, and what builds its input and drives it
+_DIGEST_FILES = {
+    "k_peel": ["csrc/peel.hip", "csrc/common.hpp", "csrc/internal.hpp", "csrc/mlp.hpp", "csrc/build.hip",
+               "csrc/scan.hip", "csrc/support.hip", "csrc/api.hip", "sched_model.json"],
+    "k_batch": ["csrc/batch.hip", "csrc/common.hpp", "csrc/internal.hpp", "csrc/api.hip"],
+}
+
+
+def source_digest(kernel="k_peel"):
+    """Digest of the sources behind `kernel` (and the C ABI header); recorded
+    traffic is valid only for the same sources."""
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1205_6693_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    pkg = os.path.join(ROOT, "paper_1205_6693_amd")
+    for f in sorted(_DIGEST_FILES[kernel]) + ["../include/truss.h"]:
+        with open(os.path.join(pkg, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -121,7 +130,7 @@ def measured_traffic(workload, kernel, launches):
         if ":" in line:
             a, b = line.split(":", 1)
             kv[a.strip()] = b.strip()
-    if kv.get("source_digest") != source_digest():
+    if kv.get("source_digest") != source_digest(kernel):
         return None
     try:
         return int(float(kv["hbm_bytes_per_launch"]))

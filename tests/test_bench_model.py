@@ -67,7 +67,7 @@ def test_traffic_lookup_needs_matching_sources(tmp_path, monkeypatch):
     f = tmp_path / "traffic_k_peel_demo.txt"
     f.write_text("hbm_bytes_per_launch: 1.5e+09\nsource_digest: 0000000000000000\n")
     assert bench.measured_traffic("demo", "k_peel", 1) is None
-    f.write_text("hbm_bytes_per_launch: 1.5e+09\nsource_digest: %s\n" % bench.source_digest())
+    f.write_text("hbm_bytes_per_launch: 1.5e+09\nsource_digest: %s\n" % bench.source_digest("k_peel"))
     assert bench.measured_traffic("demo", "k_peel", 1) == 1500000000
 
 
