@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -74,6 +75,43 @@ struct HostGraph {
 bool verbose() {
   const char* v = getenv("TRUSS_VERBOSE");
   return v && *v && *v != '0';
+}
+
+// Host threads for the scans over a subgraph (at most 16).
+int host_threads() {
+  static const int t = [] {
+    const unsigned h = std::thread::hardware_concurrency();
+    const int x = h ? (int)h : 4;
+    return x < 16 ? x : 16;
+  }();
+  return t;
+}
+
+// f(lo, hi, t) over [0, n) cut into at most host_threads() contiguous
+// pieces of at least `grain` items; piece t is [lo, hi).  Returns the pieces.
+template <typename F>
+int parallel_pieces(int64_t n, int64_t grain, F&& f) {
+  int64_t parts = (n + grain - 1) / grain;
+  if (parts > host_threads()) parts = host_threads();
+  if (parts <= 1) {
+    if (n > 0) f((int64_t)0, n, 0);
+    return n > 0 ? 1 : 0;
+  }
+  const int64_t chunk = (n + parts - 1) / parts;
+  std::vector<std::thread> th;
+  for (int t = 1; t < parts; ++t) {
+    const int64_t lo = t * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    if (lo < hi) th.emplace_back([&f, lo, hi, t] { f(lo, hi, t); });
+  }
+  f((int64_t)0, chunk < n ? chunk : n, 0);
+  for (auto& x : th) x.join();
+  return (int)parts;
+}
+constexpr int64_t kGrain = 1 << 16;
+
+template <typename T>
+void atomic_add(T* p, T v) {
+  __atomic_fetch_add(p, v, __ATOMIC_RELAXED);
 }
 
 int build_host_graph(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, HostGraph& g) {
@@ -213,6 +251,7 @@ struct Device {
   std::vector<int32_t> lid;      // n: local id of a vertex in the current subgraph, -1 otherwise
   std::vector<int32_t> touched;  // vertices with a local id
   int64_t calls = 0, h2d = 0, d2h = 0;
+  double ms_relabel = 0.0, ms_device = 0.0;  // host relabelling; copies and subgraph runs
   ~Device() {
     if (h_src) (void)hipHostFree(h_src);
   }
@@ -244,24 +283,53 @@ size_t device_layout(int64_t cap, Arena& a, Device* d) {
 int run_staged(const HostGraph& g, Device& D, const Staged& S, bool frozen, int first_level, int stop_level,
                bool want_sup, const truss_options* opts, hipStream_t s) {
   const int64_t h = (int64_t)S.ids.size();
+  const auto t0 = Clock::now();
   int32_t nl = 0;
-  for (int64_t i = 0; i < h; ++i) {
-    const int32_t e = S.ids[(size_t)i];
-    const int32_t u = g.src[e], v = g.dst[e];
-    if (D.lid[u] < 0) {
-      D.lid[u] = nl++;
-      D.touched.push_back(u);
+  if (h >= 4 * kGrain && 8 * h >= (int64_t)g.n) {
+    // large subgraphs: mark the vertices in parallel, number them in id
+    // order, then map the edges in parallel
+    int32_t* lid = D.lid.data();
+    parallel_pieces(h, kGrain, [&](int64_t lo, int64_t hi, int) {
+      for (int64_t i = lo; i < hi; ++i) {
+        const int32_t e = S.ids[(size_t)i];
+        __atomic_store_n(&lid[g.src[e]], -2, __ATOMIC_RELAXED);
+        __atomic_store_n(&lid[g.dst[e]], -2, __ATOMIC_RELAXED);
+      }
+    });
+    for (int32_t v = 0; v < g.n; ++v)
+      if (lid[v] == -2) lid[v] = nl++;
+    parallel_pieces(h, kGrain, [&](int64_t lo, int64_t hi, int) {
+      for (int64_t i = lo; i < hi; ++i) {
+        const int32_t e = S.ids[(size_t)i];
+        D.h_src[i] = lid[g.src[e]];
+        D.h_dst[i] = lid[g.dst[e]];
+        if (frozen) D.h_frozen[i] = S.flag[(size_t)i] ? 0 : 1;
+      }
+    });
+    parallel_pieces(g.n, kGrain, [&](int64_t lo, int64_t hi, int) {
+      for (int64_t v = lo; v < hi; ++v) lid[v] = -1;
+    });
+  } else {
+    for (int64_t i = 0; i < h; ++i) {
+      const int32_t e = S.ids[(size_t)i];
+      const int32_t u = g.src[e], v = g.dst[e];
+      if (D.lid[u] < 0) {
+        D.lid[u] = nl++;
+        D.touched.push_back(u);
+      }
+      if (D.lid[v] < 0) {
+        D.lid[v] = nl++;
+        D.touched.push_back(v);
+      }
+      D.h_src[i] = D.lid[u];
+      D.h_dst[i] = D.lid[v];
+      if (frozen) D.h_frozen[i] = S.flag[(size_t)i] ? 0 : 1;
     }
-    if (D.lid[v] < 0) {
-      D.lid[v] = nl++;
-      D.touched.push_back(v);
-    }
-    D.h_src[i] = D.lid[u];
-    D.h_dst[i] = D.lid[v];
-    if (frozen) D.h_frozen[i] = S.flag[(size_t)i] ? 0 : 1;
+    for (int32_t v : D.touched) D.lid[v] = -1;
+    D.touched.clear();
   }
-  for (int32_t v : D.touched) D.lid[v] = -1;
-  D.touched.clear();
+  const auto t1 = Clock::now();
+  D.ms_relabel += std::chrono::duration<double, std::milli>(t1 - t0).count();
   const size_t b = sizeof(int32_t) * (size_t)h;
   TRUSS_HIP(hipMemcpyAsync(D.d_src, D.h_src, b, hipMemcpyHostToDevice, s));
   TRUSS_HIP(hipMemcpyAsync(D.d_dst, D.h_dst, b, hipMemcpyHostToDevice, s));
@@ -290,6 +358,7 @@ int run_staged(const HostGraph& g, Device& D, const Staged& S, bool frozen, int 
   }
   TRUSS_HIP(hipStreamSynchronize(s));
   D.calls += 1;
+  D.ms_device += ms_since(t1);
   return TRUSS_OK;
 }
 
@@ -412,17 +481,44 @@ struct BottomUp {
     cnt[R.g.src[e]] -= 1;
     cnt[R.g.dst[e]] -= 1;
   }
+  // the same from several threads on distinct edges; the caller subtracts
+  // the number of edges output from left and active_left afterwards
+  void output_shared(int32_t e, int32_t k) {
+    R.truss[e] = k;
+    gone[(size_t)e] = 1;
+    atomic_add(&cnt[R.g.src[e]], -1);
+    atomic_add(&cnt[R.g.dst[e]], -1);
+  }
+  void count_outputs(int64_t c) {
+    left -= c;
+    active_left -= c;
+  }
+};
+
+// Sum of per-piece counts.
+struct PieceSums {
+  int64_t v[16] = {0};
+  int64_t total() const {
+    int64_t t = 0;
+    for (int64_t x : v) t += x;
+    return t;
+  }
 };
 
 // Procedure 5 on the candidate subgraph H (flag = internal).
 int procedure5(BottomUp& B, const Staged& H, int32_t k, int64_t* found) {
   int rc = run_staged(B.R.g, B.R.D, H, true, k, k, false, B.R.opts, B.R.s);
   if (rc) return rc;
-  for (size_t i = 0; i < H.ids.size(); ++i)
-    if (H.flag[i] && B.R.D.h_out[i] == k) {
-      B.output(H.ids[i], k);
-      *found += 1;
-    }
+  PieceSums c;
+  parallel_pieces((int64_t)H.ids.size(), kGrain, [&](int64_t lo, int64_t hi, int t) {
+    for (int64_t i = lo; i < hi; ++i)
+      if (H.flag[(size_t)i] && B.R.D.h_out[i] == k) {
+        B.output_shared(H.ids[(size_t)i], k);
+        c.v[t] += 1;
+      }
+  });
+  B.count_outputs(c.total());
+  *found += c.total();
   return TRUSS_OK;
 }
 
@@ -495,7 +591,9 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& li
   std::vector<uint8_t> inh(h, 1), cov(h, 0), mask(h, 0);
   std::vector<int64_t> deg((size_t)rows.n, 0);
   std::vector<int32_t> fidx;
-  std::vector<uint8_t> fin;
+  std::vector<std::vector<int32_t>> piece((size_t)host_threads());
+  std::vector<int64_t> moff((size_t)rows.n + 1);
+  std::vector<int32_t> mnbr(2 * h), meid(2 * h);
   Parts P;
   Staged F;
   R.st.proc9_calls += 1;
@@ -503,53 +601,97 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& li
     int64_t found = 0;
     for (size_t i = 0; i < h; ++i) cov[i] = !inh[i];  // Step 2: H' = H
     for (;;) {                                        // Step 3
-      int64_t left = 0;
       std::fill(deg.begin(), deg.end(), 0);
-      for (size_t i = 0; i < h; ++i) {
-        mask[i] = inh[i] && !cov[i];
-        if (!inh[i]) continue;
-        deg[(size_t)L.lu[i]] += 1;
-        deg[(size_t)L.lv[i]] += 1;
-        left += !cov[i];
-      }
+      PieceSums lc;
+      parallel_pieces((int64_t)h, kGrain, [&](int64_t lo, int64_t hi, int t) {
+        for (int64_t i = lo; i < hi; ++i) {
+          mask[(size_t)i] = inh[(size_t)i] && !cov[(size_t)i];
+          if (!inh[(size_t)i]) continue;
+          atomic_add(&deg[(size_t)L.lu[(size_t)i]], (int64_t)1);
+          atomic_add(&deg[(size_t)L.lv[(size_t)i]], (int64_t)1);
+          lc.v[t] += !cov[(size_t)i];
+        }
+      });
+      const int64_t left = lc.total();
       if (left == 0) break;
       R.st.proc9_scans += 1;
-      if (!grow_parts(rows, mask.data(), deg.data(), R.cap, P)) return TRUSS_E_WORKSPACE;  // Step 4
+      // rows of H' alone (same order), so that the partition walks only its edges
+      parallel_pieces(rows.n, kGrain, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t x = lo; x < hi; ++x) {
+          int64_t c = 0;
+          for (int64_t j = rows.off[x]; j < rows.end[x]; ++j) c += mask[(size_t)rows.eid[j]];
+          moff[(size_t)x + 1] = c;
+        }
+      });
+      moff[0] = 0;
+      for (int32_t x = 0; x < rows.n; ++x) moff[(size_t)x + 1] += moff[(size_t)x];
+      parallel_pieces(rows.n, kGrain, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t x = lo; x < hi; ++x) {
+          int64_t w = moff[(size_t)x];
+          for (int64_t j = rows.off[x]; j < rows.end[x]; ++j)
+            if (mask[(size_t)rows.eid[j]]) {
+              mnbr[(size_t)w] = rows.nbr[j];
+              meid[(size_t)w++] = rows.eid[j];
+            }
+        }
+      });
+      const Rows hrows{rows.n, moff.data(), moff.data() + 1, mnbr.data(), meid.data()};
+      if (!grow_parts(hrows, mask.data(), deg.data(), R.cap, P)) return TRUSS_E_WORKSPACE;  // Step 4
       int64_t covered = 0;
       for (int64_t p = 0; p < P.count(); ++p) {  // Step 5
         // Step 6: F = NS(P_p) in the current H; flag = eligible (internal to F and to H)
-        F.ids.clear();
-        F.flag.clear();
-        fidx.clear();
-        fin.clear();
-        for (int64_t q = P.start[(size_t)p]; q < P.start[(size_t)p + 1]; ++q) {
-          const int32_t v = P.order[(size_t)q];
-          for (int64_t j = rows.off[v]; j < rows.end[v]; ++j) {
-            const int32_t i = rows.eid[j], w = rows.nbr[j];
-            if (!inh[(size_t)i]) continue;
-            const bool inside = P.part[w] == p;
-            if (inside && w < v) continue;
-            F.ids.push_back(H.ids[(size_t)i]);
-            F.flag.push_back(inside && H.flag[(size_t)i] ? 1 : 0);
-            fidx.push_back(i);
-            fin.push_back(inside ? 1 : 0);
+        // local edge indices of F, gathered piecewise over the part's vertices
+        const int64_t p0 = P.start[(size_t)p], np = P.start[(size_t)p + 1] - p0;
+        for (auto& x : piece) x.clear();
+        const int pieces = parallel_pieces(np, 4096, [&](int64_t lo, int64_t hi, int t) {
+          std::vector<int32_t>& out = piece[(size_t)t];
+          for (int64_t q = lo; q < hi; ++q) {
+            const int32_t v = P.order[(size_t)(p0 + q)];
+            for (int64_t j = rows.off[v]; j < rows.end[v]; ++j) {
+              const int32_t i = rows.eid[j], w = rows.nbr[j];
+              if (!inh[(size_t)i]) continue;
+              const bool inside = P.part[w] == p;
+              if (inside && w < v) continue;
+              out.push_back(inside ? i : ~i);  // ~i: an edge leaving the part
+            }
           }
-        }
-        if (F.ids.empty()) continue;
+        });
+        fidx.clear();
+        for (int t = 0; t < pieces; ++t) fidx.insert(fidx.end(), piece[(size_t)t].begin(), piece[(size_t)t].end());
+        if (fidx.empty()) continue;
+        const int64_t nf = (int64_t)fidx.size();
+        F.ids.resize((size_t)nf);
+        F.flag.resize((size_t)nf);
+        parallel_pieces(nf, kGrain, [&](int64_t lo, int64_t hi, int) {
+          for (int64_t j = lo; j < hi; ++j) {
+            const int32_t x = fidx[(size_t)j];
+            const bool inside = x >= 0;
+            const size_t i = (size_t)(inside ? x : ~x);
+            F.ids[(size_t)j] = H.ids[i];
+            F.flag[(size_t)j] = inside && H.flag[i] ? 1 : 0;
+          }
+        });
         const int rc = run_staged(g, R.D, F, true, k, k, false, R.opts, R.s);  // Steps 7-11
         if (rc) return rc;
-        for (size_t j = 0; j < F.ids.size(); ++j) {
-          const size_t i = (size_t)fidx[j];
-          if (F.flag[j] && R.D.h_out[j] == k) {  // Step 12
-            B.output(F.ids[j], k);
-            inh[i] = 0;
-            found += 1;
+        PieceSums fc, cc;
+        parallel_pieces(nf, kGrain, [&](int64_t lo, int64_t hi, int t) {
+          for (int64_t j = lo; j < hi; ++j) {
+            const int32_t x = fidx[(size_t)j];
+            const size_t i = (size_t)(x >= 0 ? x : ~x);
+            if (F.flag[(size_t)j] && R.D.h_out[j] == k) {  // Step 12
+              B.output_shared(F.ids[(size_t)j], k);
+              inh[i] = 0;
+              fc.v[t] += 1;
+            }
+            if (x >= 0 && !cov[i]) {  // Step 13 (each internal edge of F appears once)
+              cov[i] = 1;
+              cc.v[t] += 1;
+            }
           }
-          if (fin[j] && !cov[i]) {  // Step 13
-            cov[i] = 1;
-            covered += 1;
-          }
-        }
+        });
+        B.count_outputs(fc.total());
+        found += fc.total();
+        covered += cc.total();
       }
       if (covered == 0) {
         set_last_error("procedure 9 made no progress: the budget of %lld edges is too small", (long long)R.cap);
@@ -588,6 +730,7 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
   for (int64_t e = 0; e < g.m; ++e)
     if (!phi2[(size_t)e]) sorted[(size_t)byb[lb[(size_t)e]]++] = (int32_t)e;
   std::vector<int32_t> ulist, lid((size_t)g.n, -1);
+  std::vector<std::vector<int32_t>> hpiece((size_t)host_threads());
   std::vector<uint8_t> inlist((size_t)g.n, 0);
   size_t ap = 0;
   Staged H;
@@ -616,16 +759,26 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
       else inlist[u] = 0;
     }
     ulist.resize(keep);
+    for (auto& x : hpiece) x.clear();
+    const int hp = parallel_pieces((int64_t)ulist.size(), 4096, [&](int64_t lo, int64_t hi, int t) {
+      std::vector<int32_t>& out = hpiece[(size_t)t];
+      for (int64_t q = lo; q < hi; ++q) {
+        const int32_t u = ulist[(size_t)q];
+        for (int64_t j = g.off[u]; j < g.end[u]; ++j) {
+          const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
+          if (B.gone[(size_t)e]) continue;
+          const bool inside = B.cnt[w] > 0;
+          if (inside && w < u) continue;
+          out.push_back(inside ? e : ~e);  // ~e: an external edge
+        }
+      }
+    });
     H.ids.clear();
     H.flag.clear();
-    for (const int32_t u : ulist)
-      for (int64_t j = g.off[u]; j < g.end[u]; ++j) {
-        const int32_t e = g.eid[(size_t)j], w = g.nbr[(size_t)j];
-        if (B.gone[(size_t)e]) continue;
-        const bool inside = B.cnt[w] > 0;
-        if (inside && w < u) continue;
-        H.ids.push_back(e);
-        H.flag.push_back(inside ? 1 : 0);
+    for (int t = 0; t < hp; ++t)
+      for (const int32_t x : hpiece[(size_t)t]) {
+        H.ids.push_back(x >= 0 ? x : ~x);
+        H.flag.push_back(x >= 0 ? 1 : 0);
       }
     R.st.candidates += 1;
     R.st.max_candidate = std::max(R.st.max_candidate, (int64_t)H.ids.size());
@@ -727,6 +880,10 @@ int truss_bottomup(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
   R.st.bytes_d2h = D.d2h;
   R.st.ms_total = ms_since(t0);
   if (R.st.kmax == 0 && m > 0) R.st.kmax = 2;
+  if (verbose())
+    fprintf(stderr, "truss_bottomup: %.0f ms in all: %.0f ms relabelling on the host, %.0f ms of copies and "
+            "device runs over %lld subgraphs, the rest partitioning and extraction on the host\n",
+            R.st.ms_total, D.ms_relabel, D.ms_device, (long long)D.calls);
   if (stats) *stats = R.st;
   return TRUSS_OK;
 }
