@@ -176,6 +176,20 @@ def summarize(prof_dir):
     print("\n".join(out))
 
 
+def host_info():
+    """The host the oracle was timed on: CPU model and logical CPUs."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu": model, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(sample_scale: int, seed: int):
     import graphgen
     import oracle
@@ -187,7 +201,7 @@ def cpu_baseline(sample_scale: int, seed: int):
     return {"value": s.size / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": "serial C oracle (support + Algorithm 2 bin-sort peeling), one thread, on R-MAT scale %d "
                       "edge factor 16 (same generator, m=%d) in %.1f s; full-size oracle runs take minutes"
-                      % (sample_scale, s.size, t)}
+                      % (sample_scale, s.size, t), "host": host_info()}
 
 
 def bench_batch(args):
@@ -304,7 +318,7 @@ def cpu_baseline_batch(seed: int):
         m += s.size
     return {"value": m / tot, "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": "serial C oracle, one thread, on the first 256 graphs of the batch (m=%d) in %.1f s"
-                      % (m, tot)}
+                      % (m, tot), "host": host_info()}
 
 
 def main():
