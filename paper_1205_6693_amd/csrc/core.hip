@@ -8,8 +8,10 @@
 // neighbour whose degree falls from c+1 to c is taken in the next sub-round
 // of the same level.  Taken vertices are not decremented again, so each live
 // vertex loses exactly its edges to taken vertices.  An empty level jumps to
-// the smallest live degree.  The host drives the sub-rounds (a few hundred
-// at these sizes); the work of a sub-round is a wavefront per taken vertex.
+// the smallest live degree.  Each level start and each sub-round is one
+// launch of the same step kernel (a thread per vertex at a level start, a
+// wavefront per taken vertex in a sub-round); the step's last workgroup
+// decides the next step, so launches are queued without host round trips.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -20,12 +22,28 @@ namespace {
 constexpr int kT = 256;
 constexpr int kIntMax = 0x7fffffff;
 
-struct CoreCtl {
-  int qn;     // vertices taken by this pass
-  int minv;   // smallest degree among live vertices not taken
-  int alive;  // live vertices not taken
-  int pad;
+// The peeling runs as a sequence of identical launches (steps) of one kernel;
+// the state below says what a step does.  The last workgroup to finish a step
+// decides the next one, so launches follow each other without a host round
+// trip; the host checks for the end every kStepsPerCheck launches.
+enum CorePhase : int { kStart = 0, kRound = 1, kDone = 2 };
+
+struct CoreState {
+  int phase;  // kStart: take live vertices of degree <= level; kRound: remove the queue's vertices
+  int level;
+  int cur;    // queue holding the current frontier
+  int qn;     // its length (kRound)
+  int cmax;
+  int steps;
+  // counters of the running step, cleared by the workgroup that decides
+  int next;   // vertices appended by this step
+  int alive;  // kStart: live vertices left
+  int minv;   // kStart: their smallest degree
+  unsigned arrived;
 };
+
+constexpr unsigned kStepBlocks = 1024;
+constexpr int kStepsPerCheck = 16;
 
 inline unsigned blocks(int64_t n) {
   const int64_t b = (n + kT - 1) / kT;
@@ -33,88 +51,137 @@ inline unsigned blocks(int64_t n) {
 }
 
 __global__ void k_core_init(const int64_t* __restrict__ row_ptr, int32_t n, int32_t* __restrict__ deg,
-                            int32_t* __restrict__ core) {
+                            int32_t* __restrict__ core, CoreState* st) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v < n) {
     deg[v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
     core[v] = -1;
   }
-}
-
-__global__ void k_core_ctl_reset(CoreCtl* c) {
-  if (threadIdx.x == 0) {
-    c->qn = 0;
-    c->minv = kIntMax;
-    c->alive = 0;
+  if (v == 0) {
+    st->phase = kStart;
+    st->level = 0;
+    st->cur = 0;
+    st->qn = 0;
+    st->cmax = 0;
+    st->steps = 0;
+    st->next = 0;
+    st->alive = 0;
+    st->minv = kIntMax;
+    st->arrived = 0;
   }
 }
 
-// level start: live vertices of degree <= level are taken
-__global__ void __launch_bounds__(kT) k_core_start(const int32_t* __restrict__ deg, int32_t* __restrict__ core,
-                                                   int32_t n, int level, int32_t* __restrict__ q, CoreCtl* c) {
+__global__ void __launch_bounds__(kT) k_core_step(const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col, int32_t* __restrict__ deg,
+                                                  int32_t* __restrict__ core, int32_t n, int32_t* __restrict__ q0,
+                                                  int32_t* __restrict__ q1, CoreState* st) {
   __shared__ int s_min[kT / kWave], s_cnt[kT / kWave];
-  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  bool take = false;
-  int dmin = kIntMax, alive = 0;
-  if (v < n && core[v] < 0) {
-    const int d = deg[v];
-    if (d <= level) {
-      take = true;
-      core[v] = level;
-    } else {
-      dmin = d;
-      alive = 1;
-    }
-  }
-  const int pos = wave_append(&c->qn, take);
-  if (take) q[pos] = (int32_t)v;
-  dmin = wave_min(dmin);
-  alive = wave_sum(alive);
-  const int w = threadIdx.x / kWave;
-  if (lane_id() == 0) {
-    s_min[w] = dmin;
-    s_cnt[w] = alive;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int a = 0, b = kIntMax;
-    for (int q2 = 0; q2 < kT / kWave; ++q2) {
-      a += s_cnt[q2];
-      b = s_min[q2] < b ? s_min[q2] : b;
-    }
-    if (a) atomicAdd(&c->alive, a);
-    if (b != kIntMax) atomicMin(&c->minv, b);
-  }
-}
-
-// a sub-round: every taken vertex removes its edges to live vertices
-__global__ void __launch_bounds__(kT) k_core_round(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                                   int32_t* __restrict__ deg, int32_t* __restrict__ core,
-                                                   const int32_t* __restrict__ q, int qn, int level,
-                                                   int32_t* __restrict__ nq, CoreCtl* c) {
+  __shared__ int s_last;
+  const int phase = st->phase;  // written by an earlier launch
+  if (phase == kDone) return;
+  const int level = st->level, cur = st->cur;
+  int32_t* qc = cur ? q1 : q0;
+  int32_t* qx = cur ? q0 : q1;
   const int lane = lane_id();
-  const int64_t gw = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t i = gw; i < qn; i += nw) {
-    const int32_t v = q[i];
-    const int64_t rb = row_ptr[v], re = row_ptr[v + 1];
-    for (int64_t j0 = rb; j0 < re; j0 += kWave) {
-      const int64_t j = j0 + lane;
+  if (phase == kStart) {
+    // live vertices of degree <= level are taken (core number = level)
+    int dmin = kIntMax, alive = 0;
+    for (int64_t v0 = (int64_t)blockIdx.x * kT; v0 < n; v0 += (int64_t)gridDim.x * kT) {
+      const int64_t v = v0 + threadIdx.x;
       bool take = false;
-      int32_t u = 0;
-      if (j < re) {
-        u = col[j];
-        if (__hip_atomic_load(&core[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) {
-          const int old = atomicSub(&deg[u], 1);
-          if (old == level + 1) {
-            __hip_atomic_store(&core[u], level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            take = true;
-          }
+      if (v < n && core[v] < 0) {
+        const int d = deg[v];
+        if (d <= level) {
+          take = true;
+          core[v] = level;
+        } else {
+          dmin = d < dmin ? d : dmin;
+          alive += 1;
         }
       }
-      const int pos = wave_append(&c->qn, take);
-      if (take) nq[pos] = u;
+      const int pos = wave_append(&st->next, take);
+      if (take) qc[pos] = (int32_t)v;
     }
+    dmin = wave_min(dmin);
+    alive = wave_sum(alive);
+    const int w = threadIdx.x / kWave;
+    if (lane == 0) {
+      s_min[w] = dmin;
+      s_cnt[w] = alive;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int x = 0, y = kIntMax;
+      for (int i = 0; i < kT / kWave; ++i) {
+        x += s_cnt[i];
+        y = s_min[i] < y ? s_min[i] : y;
+      }
+      if (x) atomicAdd(&st->alive, x);
+      if (y != kIntMax) atomicMin(&st->minv, y);
+    }
+  } else {
+    // every queued vertex removes its edges to live vertices; a neighbour
+    // whose degree falls from level + 1 to level joins the next queue
+    const int qn = st->qn;
+    const int64_t gw = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t i = gw; i < qn; i += nw) {
+      const int32_t v = qc[i];
+      const int64_t rb = row_ptr[v], re = row_ptr[v + 1];
+      for (int64_t j0 = rb; j0 < re; j0 += kWave) {
+        const int64_t j = j0 + lane;
+        bool take = false;
+        int32_t u = 0;
+        if (j < re) {
+          u = col[j];
+          if (__hip_atomic_load(&core[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) {
+            const int old = atomicSub(&deg[u], 1);
+            if (old == level + 1) {
+              __hip_atomic_store(&core[u], level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              take = true;
+            }
+          }
+        }
+        const int pos = wave_append(&st->next, take);
+        if (take) qx[pos] = u;
+      }
+    }
+  }
+  // the last workgroup of the step decides the next one
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&st->arrived, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    __threadfence();
+    const int next = __hip_atomic_load(&st->next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (phase == kStart) {
+      if (next == 0) {
+        if (__hip_atomic_load(&st->alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          st->phase = kDone;
+        } else {
+          // no vertex at this level: the next level is the smallest live degree
+          st->level = __hip_atomic_load(&st->minv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      } else {
+        st->cmax = level;
+        st->qn = next;
+        st->phase = kRound;
+      }
+    } else if (next == 0) {
+      st->level = level + 1;
+      st->phase = kStart;
+    } else {
+      st->cur = cur ^ 1;
+      st->qn = next;
+    }
+    st->next = 0;
+    st->alive = 0;
+    st->minv = kIntMax;
+    st->steps += 1;
+    st->arrived = 0;
   }
 }
 
@@ -174,46 +241,39 @@ size_t core_workspace(int32_t n, Arena& a) {
   a.take<int32_t>((size_t)n + 1);
   a.take<int32_t>((size_t)n + 1);
   a.take<int32_t>((size_t)n + 1);
-  a.take<CoreCtl>(1);
+  a.take<CoreState>(1);
   return a.used;
 }
 
 int compute_core_numbers(const DevGraph& dg, int32_t* core, int32_t* cmax_out, Arena& a, hipStream_t s) {
   int32_t* deg = a.take<int32_t>((size_t)dg.n + 1);
-  int32_t* q[2] = {a.take<int32_t>((size_t)dg.n + 1), a.take<int32_t>((size_t)dg.n + 1)};
-  CoreCtl* c = a.take<CoreCtl>(1);
+  int32_t* q0 = a.take<int32_t>((size_t)dg.n + 1);
+  int32_t* q1 = a.take<int32_t>((size_t)dg.n + 1);
+  CoreState* st = a.take<CoreState>(1);
   if (a.overflow()) return TRUSS_E_WORKSPACE;
   *cmax_out = 0;
   if (dg.n == 0) return TRUSS_OK;
-  hipLaunchKernelGGL(k_core_init, dim3(blocks(dg.n)), dim3(kT), 0, s, dg.row_ptr, dg.n, deg, core);
-  int level = 0, cmax = 0;
-  CoreCtl h;
-  for (;;) {
-    hipLaunchKernelGGL(k_core_ctl_reset, dim3(1), dim3(64), 0, s, c);
-    hipLaunchKernelGGL(k_core_start, dim3(blocks(dg.n)), dim3(kT), 0, s, deg, core, dg.n, level, q[0], c);
-    TRUSS_HIP(hipMemcpyAsync(&h, c, sizeof(h), hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(k_core_init, dim3(blocks(dg.n)), dim3(kT), 0, s, dg.row_ptr, dg.n, deg, core, st);
+  // a level with takes costs its start, at most one empty start before it and
+  // at most one sub-round per vertex taken: at most 3n + 1 steps in all (a
+  // guard against a stuck loop)
+  const long long max_steps = 4LL * dg.n + 2 * kStepsPerCheck;
+  CoreState h;
+  for (long long launched = 0;;) {
+    for (int i = 0; i < kStepsPerCheck; ++i)
+      hipLaunchKernelGGL(k_core_step, dim3(kStepBlocks), dim3(kT), 0, s, dg.row_ptr, dg.col, deg, core, dg.n, q0,
+                         q1, st);
+    launched += kStepsPerCheck;
+    TRUSS_HIP(hipMemcpyAsync(&h, st, sizeof(h), hipMemcpyDeviceToHost, s));
     TRUSS_HIP(hipStreamSynchronize(s));
-    if (h.qn == 0) {
-      if (h.alive == 0) break;
-      level = h.minv;  // no vertex at this level: the next level is the smallest live degree
-      continue;
+    if (h.phase == kDone) break;
+    if (launched > max_steps) {
+      set_last_error("core numbers did not finish within %lld steps", max_steps);
+      return TRUSS_E_INTERNAL;
     }
-    cmax = level;
-    int cur = 0, qn = h.qn;
-    while (qn > 0) {
-      hipLaunchKernelGGL(k_core_ctl_reset, dim3(1), dim3(64), 0, s, c);
-      const int64_t waves = qn < 65536 ? qn : 65536;
-      hipLaunchKernelGGL(k_core_round, dim3(blocks(waves * kWave)), dim3(kT), 0, s, dg.row_ptr, dg.col, deg, core,
-                         q[cur], qn, level, q[cur ^ 1], c);
-      TRUSS_HIP(hipMemcpyAsync(&h, c, sizeof(h), hipMemcpyDeviceToHost, s));
-      TRUSS_HIP(hipStreamSynchronize(s));
-      cur ^= 1;
-      qn = h.qn;
-    }
-    ++level;
   }
   TRUSS_HIP(hipGetLastError());
-  *cmax_out = cmax;
+  *cmax_out = h.cmax;
   return TRUSS_OK;
 }
 
