@@ -107,14 +107,20 @@ _DIGEST_FILES = {
 
 
 def source_digest(kernel="k_peel"):
-    """Digest of the sources behind `kernel` (and the C ABI header); recorded
-    traffic is valid only for the same sources."""
+    """Digest of the code behind `kernel` (and the C ABI header), comments
+    left out; recorded traffic is valid only for the same code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_1205_6693_amd")
     for f in sorted(_DIGEST_FILES[kernel]) + ["../include/truss.h"]:
         with open(os.path.join(pkg, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+            text = fh.read()
+        if not f.endswith(".json"):
+            text = re.sub(rb"/\*.*?\*/", b"", text, flags=re.S)
+            text = re.sub(rb"//[^\n]*", b"", text)
+            text = b"\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(f.encode() + text)
     return h.hexdigest()[:16]
 
 

@@ -313,8 +313,8 @@ typedef struct truss_bottomup_stats {
 /* Device workspace for a budget of cap edges per subgraph (1 <= cap <= INT32_MAX). */
 int truss_bottomup_workspace_size(int64_t cap, size_t *bytes);
 /* src, dst (host): the m edges over vertices 0..n-1 (validated: ids in range,
- * no self-loop, no pair twice).  first_part (host, nullable): part id >= 0 of
- * every vertex with an edge, for the first LowerBounding pass instead of the
+ * no self-loop, no pair twice).  first_part (host, nullable): part id in [0, n)
+ * of every vertex with an edge, for the first LowerBounding pass instead of the
  * grown parts (each part's neighbourhood subgraph must fit in cap).
  * truss_out (host) int32[m]: phi(e) by input index; lower_out (host,
  * nullable) int32[m]: the bound from LowerBounding.  opts as for

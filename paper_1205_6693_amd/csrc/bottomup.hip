@@ -392,8 +392,8 @@ int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, 
       P.part.assign((size_t)g.n, -1);
       for (int32_t v = 0; v < g.n; ++v) {
         if (deg[v] == 0) continue;
-        if (first_part[v] < 0) {
-          set_last_error("vertex %d has edges but no part", v);
+        if (first_part[v] < 0 || first_part[v] >= g.n) {
+          set_last_error("vertex %d has edges but no part id in [0, n)", v);
           return TRUSS_E_INVAL;
         }
         P.part[v] = first_part[v];

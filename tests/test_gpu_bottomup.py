@@ -81,6 +81,10 @@ def test_errors():
     bad[3] = -1
     with pytest.raises(T.TrussError):  # a vertex with edges and no part
         T.truss_bottomup(n, s, d, 1000, bad)
+    big = np.zeros(n, np.int32)
+    big[0] = n
+    with pytest.raises(T.TrussError):  # a part id outside [0, n)
+        T.truss_bottomup(n, s, d, 1000, big)
     with pytest.raises(T.TrussError):  # a part whose subgraph exceeds the budget
         T.truss_bottomup(n, s, d, 20, np.zeros(n, np.int32))
     with pytest.raises(T.TrussError):  # self-loop
