@@ -12,6 +12,7 @@ Usage: python tests/golden/make_golden.py rmat20      (about 5 minutes, one core
        python tests/golden/make_golden.py chunglu4m   (the 57M-edge Chung-Lu graph; about 8 minutes)
        python tests/golden/make_golden.py rmat24      (260M edges; hours, about 30 GB of RAM)
        python tests/golden/make_golden.py batch4096   (the 4096-graph batch; five processes)
+       python tests/golden/make_golden.py --core rmat24  (core numbers only, added to an existing record)
 """
 import hashlib
 import os
@@ -109,9 +110,30 @@ def main(name):
     print("\n".join(lines))
 
 
+def core_main(name):
+    """Adds the core-number digest and c_max to an existing record (for
+    records written before those fields existed; the truss numbers the
+    cohesion statistics need are not recomputed)."""
+    path = os.path.join(HERE, "oracle_%s.txt" % name)
+    text = open(path).read()
+    if "core_sha256:" in text:
+        print("record already has core numbers")
+        return
+    n, s, d = WORKLOADS[name]()
+    t0 = time.time()
+    core, cmax = oracle.core_numbers(n, s, d)
+    lines = ["# core numbers added by tests/golden/make_golden.py --core %s from oracle.core_numbers (%.0f s)"
+             % (name, time.time() - t0), "core_sha256: %s" % digest(core), "cmax: %d" % cmax]
+    with open(path, "a") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "rmat20"
     if which == "batch4096":
         batch_main()
+    elif which == "--core":
+        core_main(sys.argv[2])
     else:
         main(which)

@@ -112,7 +112,8 @@ def test_cohesion_degenerate():
 
 
 FULL = {"er2000": lambda: graphgen.er_small(1), "rmat16": lambda: graphgen.rmat(16, 16, 1),
-        "rmat20": lambda: graphgen.rmat20(1), "chunglu4m": lambda: graphgen.chung_lu4m(1)}
+        "rmat20": lambda: graphgen.rmat20(1), "chunglu4m": lambda: graphgen.chung_lu4m(1),
+        "rmat24": lambda: graphgen.rmat24(1)}
 
 
 @pytest.mark.parametrize("name", list(FULL))
@@ -127,7 +128,8 @@ def test_core_and_cohesion_full_size(name):
     core, cmax = T.truss_core_numbers(g)
     assert golden_io.int32_digest(core.cpu().numpy()) == rec["core_sha256"]
     assert cmax == rec["cmax"]
-    _check_cohesion(T.truss_cohesion(g), rec["cohesion"])
+    if "cohesion" in rec:  # the R-MAT 24 record holds the core numbers only
+        _check_cohesion(T.truss_cohesion(g), rec["cohesion"])
 
 
 def test_truss_inside_core_at_size():
