@@ -40,7 +40,8 @@ def test_upper_bound_matches_oracle():
 
 
 FULL = {"er2000": lambda: graphgen.er_small(1), "rmat16": lambda: graphgen.rmat(16, 16, 1),
-        "rmat20": lambda: graphgen.rmat20(1), "chunglu4m": lambda: graphgen.chung_lu4m(1)}
+        "rmat20": lambda: graphgen.rmat20(1), "chunglu4m": lambda: graphgen.chung_lu4m(1),
+        "rmat24": lambda: graphgen.rmat24(1)}
 
 
 @pytest.mark.parametrize("name", list(FULL))
