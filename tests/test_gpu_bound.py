@@ -100,3 +100,28 @@ def test_topdown_planted_cliques_small_subgraph():
     assert gmax == kmax and gmin == kmin
     np.testing.assert_array_equal(got.cpu().numpy(), ref)
     assert st["m"] < s.size // 10
+
+
+@pytest.mark.parametrize("name", ["rmat20", "chunglu4m", "rmat24"])
+def test_topdown_full_size(name):
+    """The top-t classes at full size: the full decomposition is checked against
+    the oracle's digest and class sizes, and the top-down output must equal its
+    classes above k_max - t (zero elsewhere)."""
+    import torch
+    rec = golden_io.oracle_record(name)
+    if rec is None:
+        pytest.skip("no record for " + name)
+    T = lib()
+    n, s, d = FULL[name]()
+    g = csr_graph(n, s, d)
+    phi, st = T.truss_decompose(g)
+    assert golden_io.int32_digest(phi.cpu().numpy()) == rec["truss_sha256"]
+    for t in (1, 3, 10):
+        say(f"case: top-{t} classes at full size, {name}")
+        got, kmin, kmax, tst = T.truss_topdown(g, t)
+        assert kmax == rec["kmax"] and kmin == max(2, kmax - t + 1)
+        ref = torch.where(phi >= kmin, phi, torch.zeros_like(phi))
+        assert torch.equal(got, ref)
+        sizes = {k: int(c) for k, c in rec["class_sizes"].items() if k >= kmin}
+        vals, cnts = torch.unique(got[got > 0], return_counts=True)
+        assert dict(zip(vals.tolist(), cnts.tolist())) == sizes
