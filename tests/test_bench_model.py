@@ -76,3 +76,21 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120, env=dict(os.environ, HIP_VISIBLE_DEVICES=""))
     assert r.returncode != 0
     assert "--gpus 1" in r.stderr
+
+
+def test_digest_ignores_comments_only(tmp_path, monkeypatch):
+    import shutil
+    pkg = tmp_path / "paper_1205_6693_amd"
+    shutil.copytree(os.path.join(ROOT, "paper_1205_6693_amd", "csrc"), pkg / "csrc")
+    shutil.copy(os.path.join(ROOT, "paper_1205_6693_amd", "sched_model.json"), pkg / "sched_model.json")
+    (tmp_path / "include").mkdir()
+    shutil.copy(os.path.join(ROOT, "include", "truss.h"), tmp_path / "include" / "truss.h")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base, batch = bench.source_digest("k_peel"), bench.source_digest("k_batch")
+    peel = pkg / "csrc" / "peel.hip"
+    text = peel.read_text()
+    peel.write_text(text + "\n// a comment\n/* another\n comment */\n")
+    assert bench.source_digest("k_peel") == base
+    peel.write_text(text.replace("kMinChunk = 64", "kMinChunk = 32"))
+    assert bench.source_digest("k_peel") != base
+    assert bench.source_digest("k_batch") == batch  # the batch kernel does not depend on peel.hip
