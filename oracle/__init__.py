@@ -214,8 +214,9 @@ def cohesion(n: int, src, dst, phi=None, core=None):
 def lower_bounding(n: int, src, dst, cap: int, first_part=None):
     """Algorithm 3: (lb[m], phi2[m] as bool, info) where lb is the lower bound
     of every edge and phi2 marks the edges output as Phi_2.  cap = most edges
-    a neighbourhood subgraph may hold; first_part (optional) = part id of every
-    vertex for the first pass (later passes use the sequential partition)."""
+    a neighbourhood subgraph may hold; first_part (optional) = part id in
+    [0, n) of every vertex with an edge, for the first pass (later passes
+    use the sequential partition)."""
     src, dst = _edges(src, dst)
     rc = _load().oracle_validate_edges(n, src.size, src, dst)
     if rc:

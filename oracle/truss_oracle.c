@@ -691,7 +691,7 @@ int oracle_lower_bounding(int32_t n, int64_t m, const int32_t *src, const int32_
       parts = 0;
       for (int32_t v = 0; v < n; ++v) {
         part[v] = active[v] ? first_part[v] : -1;
-        if (active[v] && first_part[v] < 0) { rc = -OR_INVAL; goto out; }
+        if (active[v] && (first_part[v] < 0 || first_part[v] >= n)) { rc = -OR_INVAL; goto out; }
         if (part[v] + 1 > parts) parts = part[v] + 1;
       }
     } else {

@@ -124,3 +124,20 @@ def test_budget_below_a_degree_is_refused():
     with pytest.raises(oracle.OracleError) as e:
         oracle.lower_bounding(n, s, d, cap=6)  # vertex d has degree 7
     assert -e.value.code == oracle.CAP
+
+
+def test_part_ids_outside_range_are_refused():
+    # the caller's partition names every vertex with an edge by a part id in
+    # [0, n), as the library's boundary requires; vertices without edges are
+    # not read
+    n, s, d, _, _, part = _example3()
+    for bad in (-1, n, n + 7):
+        p = part.copy()
+        p[int(s[0])] = bad
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.lower_bounding(n, s, d, cap=40, first_part=p)
+        assert -e.value.code == oracle.INVAL
+    iso = np.concatenate([part, np.array([n + 5], np.int32)])  # an isolated vertex n
+    lb, _, _ = oracle.lower_bounding(n + 1, s, d, cap=40, first_part=iso)
+    lb0, _, _ = oracle.lower_bounding(n, s, d, cap=40, first_part=part)
+    assert (lb == lb0).all()
