@@ -199,6 +199,37 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
 
 
+def _dev(t, name, dtype, numel=0, device=None):
+    """Checks that t is a contiguous CUDA tensor of dtype holding at least
+    numel elements (on `device` when given): the library dereferences it on
+    the GPU and cannot check any of this itself."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be in device memory (got %s)" % (name, t.device))
+    if device is not None and t.device != torch.device(device):
+        raise ValueError("%s is on %s, the rest on %s" % (name, t.device, device))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ValueError("%s holds %d elements, %d needed" % (name, t.numel(), numel))
+    return t
+
+
+def _ws_bytes(ws, device=None):
+    """Size in bytes of a workspace tensor (any dtype; the library checks
+    that it is large enough)."""
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor) or ws.device.type != "cuda" or not ws.is_contiguous():
+        raise ValueError("the workspace must be a contiguous tensor in device memory")
+    if device is not None and ws.device != torch.device(device):
+        raise ValueError("the workspace is on %s, the rest on %s" % (ws.device, device))
+    return ws.numel() * ws.element_size()
+
+
 def _stream(stream):
     torch = _torch()
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -219,6 +250,8 @@ class Graph:
         dst = dst.to(torch.int32).contiguous()
         if src.shape != dst.shape or src.dim() != 1:
             raise ValueError("src and dst must be 1-D and of equal length")
+        _dev(src, "src", torch.int32)
+        _dev(dst, "dst", torch.int32, device=src.device)
         return cls(n, src.numel(), FMT_EDGES, src=src, dst=dst)
 
     @classmethod
@@ -228,6 +261,10 @@ class Graph:
         col = col.to(torch.int32).contiguous()
         if col.numel() % 2:
             raise ValueError("a symmetric CSR has an even number of entries")
+        if row_ptr.dim() != 1 or row_ptr.numel() != int(n) + 1 or col.dim() != 1:
+            raise ValueError("row_ptr must hold n + 1 offsets and col be 1-D")
+        _dev(row_ptr, "row_ptr", torch.int64)
+        _dev(col, "col", torch.int32, device=row_ptr.device)
         return cls(n, col.numel() // 2, FMT_CSR, row_ptr=row_ptr, col=col)
 
     def _c(self):
@@ -253,6 +290,9 @@ def make_options(support_strategy=SUP_AUTO, peel_mode=PEEL_AUTO, scheduler=SCHED
     o.support_strategy, o.peel_mode, o.scheduler = support_strategy, peel_mode, scheduler
     o.peel_probe = peel_probe
     o.batch_block, o.batch_ilp = batch_block, batch_ilp
+    if model is not None:
+        _dev(model, "model", _torch().float32, 4)
+        o._model = model  # the options hold its address: keep it alive with them
     o.model = _ptr(model).value if model is not None else None
     o.max_subrounds, o.grid_blocks = max_subrounds, grid_blocks
     return o
@@ -277,11 +317,12 @@ def truss_support(graph: Graph, out=None, ws=None, stream=None):
     lib = load_library()
     if out is None:
         out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    _dev(out, "out", torch.int32, graph.m, graph.device)
     if ws is None:
         ws = workspace(graph)
     tri = ctypes.c_int64(0)
     g = graph._c()
-    _check(lib.truss_support(ctypes.byref(g), _ptr(out), ctypes.byref(tri), _ptr(ws), ws.numel(),
+    _check(lib.truss_support(ctypes.byref(g), _ptr(out), ctypes.byref(tri), _ptr(ws), _ws_bytes(ws, graph.device),
                              _stream(stream)))
     return out, tri.value
 
@@ -292,12 +333,13 @@ def truss_decompose(graph: Graph, opts: Options | None = None, out=None, ws=None
     lib = load_library()
     if out is None:
         out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    _dev(out, "out", torch.int32, graph.m, graph.device)
     if ws is None:
         ws = workspace(graph, opts)
     st = Stats()
     g = graph._c()
     _check(lib.truss_decompose(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
-                               ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream)))
+                               ctypes.byref(st), _ptr(ws), _ws_bytes(ws, graph.device), _stream(stream)))
     return out, st.to_dict()
 
 
@@ -319,8 +361,16 @@ def _batch_args(vtx_off, edge_off, src, dst, out):
     eo = np.ascontiguousarray(edge_off, dtype=np.int64)
     src = src.to(torch.int32).contiguous()
     dst = dst.to(torch.int32).contiguous()
+    if vo.ndim != 1 or vo.size < 1 or eo.shape != vo.shape:
+        raise ValueError("vtx_off and edge_off must hold one offset per graph plus one")
+    total = int(eo[-1])
+    if src.dim() != 1 or src.shape != dst.shape or src.numel() < total:
+        raise ValueError("src and dst must be 1-D, of equal length and hold edge_off[-1] edges")
+    _dev(src, "src", torch.int32)
+    _dev(dst, "dst", torch.int32, device=src.device)
     if out is None:
         out = torch.empty(src.numel(), dtype=torch.int32, device=src.device)
+    _dev(out, "out", torch.int32, total, src.device)
     return vo, eo, src, dst, out
 
 
@@ -334,8 +384,8 @@ def truss_batch(vtx_off, edge_off, src, dst, opts: Options | None = None, out=No
                          device=src.device)
     st = Stats()
     _check(lib.truss_batch(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
-                           ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
-                           _stream(stream)))
+                           ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
+                           _ws_bytes(ws, src.device), _stream(stream)))
     return out, st.to_dict()
 
 
@@ -354,7 +404,8 @@ class BatchPlan:
         h = ctypes.c_void_p(0)
         _check(lib.truss_batch_plan_create(len(self.vo) - 1, self.vo.ctypes.data, self.eo.ctypes.data,
                                            _ptr(self.src), _ptr(self.dst), _ptr(self.out),
-                                           ctypes.byref(opts) if opts else None, _ptr(self.ws), self.ws.numel(),
+                                           ctypes.byref(opts) if opts else None, _ptr(self.ws),
+                                           _ws_bytes(self.ws, self.src.device),
                                            _stream(stream), ctypes.byref(h)))
         self._h = h
 
@@ -386,7 +437,8 @@ def truss_batch_autotune(vtx_off, edge_off, src, dst, opts: Options | None = Non
         ws = torch.empty(max(1, truss_batch_workspace_size(vo, eo, opts)), dtype=torch.uint8, device=src.device)
     tb, tl, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
     _check(lib.truss_batch_autotune(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
-                                    ctypes.byref(opts) if opts else None, _ptr(ws), ws.numel(), _stream(stream),
+                                    ctypes.byref(opts) if opts else None, _ptr(ws), _ws_bytes(ws, src.device),
+                                    _stream(stream),
                                     ctypes.byref(tb), ctypes.byref(tl), ctypes.byref(ms)))
     return tb.value, tl.value, ms.value
 
@@ -400,6 +452,7 @@ def truss_decompose_traced(graph: Graph, opts: Options | None = None, level_cap:
     lib = load_library()
     if out is None:
         out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    _dev(out, "out", torch.int32, graph.m, graph.device)
     if ws is None:
         ws = workspace(graph, opts)
     feat = torch.zeros((max(level_cap, 1), SCHED_PEEL_F), dtype=torch.float32, device=graph.device)
@@ -411,7 +464,7 @@ def truss_decompose_traced(graph: Graph, opts: Options | None = None, level_cap:
     st = Stats()
     g = graph._c()
     _check(lib.truss_decompose_traced(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
-                                      ctypes.byref(st), ctypes.byref(tr), _ptr(ws), ws.numel(),
+                                      ctypes.byref(st), ctypes.byref(tr), _ptr(ws), _ws_bytes(ws, graph.device),
                                       _stream(stream)))
     L = tr.levels
     trace = {"levels": L,
@@ -449,9 +502,11 @@ def mlp_forward(params, X, H: int, O: int, stream=None):
     X = _f32(X)
     params = _f32(params)
     B, F = X.shape
+    _dev(X, "X", torch.float32)
+    _dev(params, "params", torch.float32, mlp_param_count(F, H, O), X.device)
     Y = torch.empty((B, O), dtype=torch.float32, device=X.device)
     ws = _mlp_ws(F, H, O, B, X.device)
-    _check(load_library().truss_mlp_forward(_ptr(params), F, H, O, _ptr(X), B, _ptr(Y), _ptr(ws), ws.numel(),
+    _check(load_library().truss_mlp_forward(_ptr(params), F, H, O, _ptr(X), B, _ptr(Y), _ptr(ws), _ws_bytes(ws),
                                             _stream(stream)))
     return Y
 
@@ -462,10 +517,15 @@ def mlp_backward(params, X, dY, H: int, stream=None):
     X, dY, params = _f32(X), _f32(dY), _f32(params)
     B, F = X.shape
     O = dY.shape[1]
+    if dY.shape != (B, O):
+        raise ValueError("dY must be B x O")
+    _dev(X, "X", torch.float32)
+    _dev(dY, "dY", torch.float32, device=X.device)
+    _dev(params, "params", torch.float32, mlp_param_count(F, H, O), X.device)
     grad = torch.empty(params.numel(), dtype=torch.float32, device=X.device)
     ws = _mlp_ws(F, H, O, B, X.device)
     _check(load_library().truss_mlp_backward(_ptr(params), F, H, O, _ptr(X), B, _ptr(dY), _ptr(grad), _ptr(ws),
-                                             ws.numel(), _stream(stream)))
+                                             _ws_bytes(ws), _stream(stream)))
     return grad
 
 
@@ -473,14 +533,23 @@ def mlp_train(params, adam_m, adam_v, X, T, Wt, H: int, steps: int, step0: int =
               stream=None):
     """Adam steps on the weighted squared error, in place on params/adam_m/adam_v
     (contiguous CUDA float32 tensors); returns the final loss."""
+    torch = _torch()
     X, T, Wt = _f32(X), _f32(T), _f32(Wt)
     B, F = X.shape
     O = T.shape[1]
+    if T.shape != (B, O) or Wt.shape != (B, O):
+        raise ValueError("T and Wt must be B x O")
+    _dev(X, "X", torch.float32)
+    _dev(T, "T", torch.float32, device=X.device)
+    _dev(Wt, "Wt", torch.float32, device=X.device)
+    P = mlp_param_count(F, H, O)
+    for t, name in ((params, "params"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+        _dev(t, name, torch.float32, P, X.device)  # updated in place
     ws = _mlp_ws(F, H, O, B, X.device)
     loss = ctypes.c_float(0.0)
     _check(load_library().truss_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), F, H, O, _ptr(X), _ptr(T),
                                           _ptr(Wt), B, steps, step0, lr, ctypes.byref(loss), _ptr(ws),
-                                          ws.numel(), _stream(stream)))
+                                          _ws_bytes(ws), _stream(stream)))
     return loss.value
 
 
@@ -501,14 +570,19 @@ def sched_train(kind: int, X, T_ms, H: int = 32, steps: int = 3000, lr: float = 
     X, T_ms = _f32(X), _f32(T_ms)
     B = X.shape[0]
     n = sched_part_floats(kind, H)
+    if X.dim() != 2 or T_ms.dim() != 2 or T_ms.shape[0] != B:
+        raise ValueError("X and T_ms must be 2-D with one row per decision")
+    _dev(X, "X", torch.float32)
+    _dev(T_ms, "T_ms", torch.float32, device=X.device)
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=X.device)
+    _dev(out, "out", torch.float32, n, X.device)
     b = ctypes.c_size_t(0)
     _check(lib.truss_sched_train_workspace_size(kind, H, B, ctypes.byref(b)))
     ws = torch.empty(b.value, dtype=torch.uint8, device=X.device)
     loss = ctypes.c_float(0.0)
     _check(lib.truss_sched_train(kind, _ptr(X), _ptr(T_ms), B, H, steps, lr, seed, _ptr(out),
-                                 ctypes.byref(loss), _ptr(ws), ws.numel(), _stream(stream)))
+                                 ctypes.byref(loss), _ptr(ws), _ws_bytes(ws), _stream(stream)))
     return out, loss.value
 
 
@@ -518,10 +592,12 @@ def truss_upper_bound(graph: Graph, out=None, ws=None, stream=None):
     lib = load_library()
     if out is None:
         out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    _dev(out, "out", torch.int32, graph.m, graph.device)
     if ws is None:
         ws = workspace(graph)
     g = graph._c()
-    _check(lib.truss_upper_bound(ctypes.byref(g), _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    _check(lib.truss_upper_bound(ctypes.byref(g), _ptr(out), _ptr(ws), _ws_bytes(ws, graph.device),
+                                 _stream(stream)))
     return out
 
 
@@ -531,6 +607,7 @@ def truss_topdown(graph: Graph, t: int, opts: Options | None = None, out=None, w
     lib = load_library()
     if out is None:
         out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    _dev(out, "out", torch.int32, graph.m, graph.device)
     g = graph._c()
     if ws is None:
         b = ctypes.c_size_t(0)
@@ -540,8 +617,8 @@ def truss_topdown(graph: Graph, t: int, opts: Options | None = None, out=None, w
     kmin, kmax = ctypes.c_int32(0), ctypes.c_int32(0)
     st = Stats()
     _check(lib.truss_topdown(ctypes.byref(g), t, _ptr(out), ctypes.byref(kmin), ctypes.byref(kmax),
-                             ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
-                             _stream(stream)))
+                             ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
+                             _ws_bytes(ws, graph.device), _stream(stream)))
     return out, kmin.value, kmax.value, st.to_dict()
 
 
@@ -552,14 +629,15 @@ def truss_core_numbers(graph: Graph, out=None, ws=None, stream=None):
     lib = load_library()
     if out is None:
         out = torch.empty(max(graph.n, 1), dtype=torch.int32, device=graph.device)
+    _dev(out, "out", torch.int32, graph.n, graph.device)
     g = graph._c()
     if ws is None:
         b = ctypes.c_size_t(0)
         _check(lib.truss_core_workspace_size(ctypes.byref(g), ctypes.byref(b)))
         ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
     cmax = ctypes.c_int32(0)
-    _check(lib.truss_core_numbers(ctypes.byref(g), _ptr(out), ctypes.byref(cmax), _ptr(ws), ws.numel(),
-                                  _stream(stream)))
+    _check(lib.truss_core_numbers(ctypes.byref(g), _ptr(out), ctypes.byref(cmax), _ptr(ws),
+                                  _ws_bytes(ws, graph.device), _stream(stream)))
     return out[:graph.n], cmax.value
 
 
@@ -575,7 +653,7 @@ def truss_cohesion(graph: Graph, opts: Options | None = None, ws=None, stream=No
         ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
     st = CohesionStats()
     _check(lib.truss_cohesion(ctypes.byref(g), ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
-                              ws.numel(), _stream(stream)))
+                              _ws_bytes(ws, graph.device), _stream(stream)))
     return st.to_dict()
 
 
@@ -591,8 +669,12 @@ def truss_bottomup(n: int, src, dst, cap: int, first_part=None, opts: Options | 
     lib = load_library()
     src = np.ascontiguousarray(src, dtype=np.int32)
     dst = np.ascontiguousarray(dst, dtype=np.int32)
+    if src.ndim != 1 or src.shape != dst.shape:
+        raise ValueError("src and dst must be 1-D and of equal length")
     m = src.size
     fp = None if first_part is None else np.ascontiguousarray(first_part, dtype=np.int32)
+    if fp is not None and fp.shape != (max(int(n), 0),):
+        raise ValueError("first_part must hold one part id per vertex")
     if ws is None:
         b = ctypes.c_size_t(0)
         _check(lib.truss_bottomup_workspace_size(int(cap), ctypes.byref(b)))
@@ -602,7 +684,7 @@ def truss_bottomup(n: int, src, dst, cap: int, first_part=None, opts: Options | 
     st = BottomUpStats()
     _check(lib.truss_bottomup(int(n), m, src.ctypes.data, dst.ctypes.data,
                               None if fp is None else fp.ctypes.data, int(cap), out.ctypes.data, low.ctypes.data,
-                              ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), ws.numel(),
+                              ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), _ws_bytes(ws),
                               _stream(stream)))
     return out[:m], low[:m], st.to_dict()
 
@@ -615,11 +697,13 @@ def truss_cohen(graph: Graph, out=None, ws=None, stream=None):
     lib = load_library()
     if out is None:
         out = torch.empty(graph.m, dtype=torch.int32, device=graph.device)
+    _dev(out, "out", torch.int32, graph.m, graph.device)
     g = graph._c()
     if ws is None:
         b = ctypes.c_size_t(0)
         _check(lib.truss_cohen_workspace_size(ctypes.byref(g), ctypes.byref(b)))
         ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
     st = Stats()
-    _check(lib.truss_cohen(ctypes.byref(g), _ptr(out), ctypes.byref(st), _ptr(ws), ws.numel(), _stream(stream)))
+    _check(lib.truss_cohen(ctypes.byref(g), _ptr(out), ctypes.byref(st), _ptr(ws), _ws_bytes(ws, graph.device),
+                           _stream(stream)))
     return out, st.to_dict()

@@ -194,6 +194,36 @@ def test_bottomup_sizes_and_errors(T):
                               ctypes.byref(st), 4096, 1 << 40, None) == T.E_RANGE
 
 
+def test_binding_refuses_what_the_library_cannot_check(T):
+    """The library dereferences the binding's tensors on the device: host
+    tensors, wrong sizes and wrong lengths are refused in Python first."""
+    import numpy as np
+    import torch
+    s = torch.tensor([0, 1], dtype=torch.int32)
+    d = torch.tensor([1, 2], dtype=torch.int32)
+    with pytest.raises(ValueError, match="device memory"):
+        T.Graph.from_edges(3, s, d)
+    with pytest.raises(ValueError):
+        T.Graph.from_edges(3, s, d[:1])
+    with pytest.raises(ValueError, match="n . 1 offsets"):
+        T.Graph.from_csr(3, torch.tensor([0, 1, 2], dtype=torch.int64), torch.tensor([1, 0], dtype=torch.int32))
+    with pytest.raises(ValueError, match="device memory"):
+        T.Graph.from_csr(2, torch.tensor([0, 1, 2], dtype=torch.int64), torch.tensor([1, 0], dtype=torch.int32))
+    with pytest.raises(ValueError, match="model"):
+        T.make_options(model=torch.zeros(8))
+    with pytest.raises(ValueError, match="edge_off"):  # 3 edges named, 2 given
+        T.truss_batch([0, 3], [0, 3], s, d)
+    with pytest.raises(ValueError, match="offset per graph"):
+        T.truss_batch([0, 3], [0, 1, 2], s, d)
+    with pytest.raises(ValueError, match="device memory"):
+        T.truss_batch([0, 3], [0, 2], s, d)
+    sn, dn = np.array([0, 1], np.int32), np.array([1, 2], np.int32)
+    with pytest.raises(ValueError, match="one part id per vertex"):
+        T.truss_bottomup(3, sn, dn, 10, first_part=np.zeros(2, np.int32))
+    with pytest.raises(ValueError):
+        T.truss_bottomup(3, sn, dn[:1], 10)
+
+
 def test_cohen_workspace(T):
     lib = T.load_library()
     b = ctypes.c_size_t(0)
