@@ -14,7 +14,10 @@
  * Conventions shared by every entry point
  *   - Pointers marked (device) are HIP device pointers; (host) are host
  *     pointers.  The caller owns every buffer; the library never frees or
- *     keeps caller memory and holds no state between calls.
+ *     keeps caller memory and holds no state between calls.  The library
+ *     checks device pointers for NULL only: a host pointer, or a buffer
+ *     shorter than an entry point states, is the caller's error and is not
+ *     detected (the Python binding checks these before every call).
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     All device work is ordered on it, and every call returns only after the
  *     stream has synchronised, so the returned status is final.
