@@ -58,7 +58,7 @@ extern "C" {
 #define TRUSS_E_UNSORTED (-6)   /* CSR row not ascending                        */
 #define TRUSS_E_DUP (-7)        /* edge listed twice (either orientation)       */
 #define TRUSS_E_ASYM (-8)       /* CSR has (u,v) without (v,u)                  */
-#define TRUSS_E_NOMEM (-9)      /* device allocation failed                     */
+#define TRUSS_E_NOMEM (-9)      /* device (or bottom-up host) allocation failed */
 #define TRUSS_E_WORKSPACE (-10) /* workspace missing or smaller than required   */
 #define TRUSS_E_DEVICE (-11)    /* HIP runtime error                            */
 #define TRUSS_E_INTERNAL (-12)  /* internal limit hit (e.g. sub-round cap)      */
@@ -323,8 +323,11 @@ int truss_bottomup_workspace_size(int64_t cap, size_t *bytes);
  * nullable) int32[m]: the bound from LowerBounding.  opts as for
  * truss_decompose (nullable).  ws (device): truss_bottomup_workspace_size
  * bytes.  Synchronises the stream; allocates pinned host staging of 17 bytes
- * per budget edge for the call.  TRUSS_E_WORKSPACE when a vertex alone, a
- * given part, or every part of a pass leaves no internal edge within cap. */
+ * per budget edge for the call, and host memory in proportion to m (the
+ * adjacency, the bounds, the candidate rows), used by up to 16 host threads.
+ * TRUSS_E_WORKSPACE when a vertex alone, a given part, or every part of a
+ * pass leaves no internal edge within cap; TRUSS_E_NOMEM when host memory
+ * runs out (TRUSS_E_INTERNAL if a host thread cannot start). */
 int truss_bottomup(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int32_t *first_part,
                    int64_t cap, int32_t *truss_out, int32_t *lower_out, const truss_options *opts,
                    truss_bottomup_stats *stats, void *ws, size_t ws_bytes, void *stream);

@@ -29,6 +29,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <exception>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -98,13 +100,31 @@ int parallel_pieces(int64_t n, int64_t grain, F&& f) {
     return n > 0 ? 1 : 0;
   }
   const int64_t chunk = (n + parts - 1) / parts;
+  // an exception in a piece (a failed allocation) is carried to the caller
+  // once every started thread has been joined
+  std::vector<std::exception_ptr> err((size_t)parts);
+  auto piece = [&f, &err](int64_t lo, int64_t hi, int t) {
+    try {
+      f(lo, hi, t);
+    } catch (...) {
+      err[(size_t)t] = std::current_exception();
+    }
+  };
   std::vector<std::thread> th;
-  for (int t = 1; t < parts; ++t) {
-    const int64_t lo = t * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    if (lo < hi) th.emplace_back([&f, lo, hi, t] { f(lo, hi, t); });
+  try {
+    th.reserve((size_t)parts);
+    for (int t = 1; t < parts; ++t) {
+      const int64_t lo = t * chunk, hi = lo + chunk < n ? lo + chunk : n;
+      if (lo < hi) th.emplace_back(piece, lo, hi, t);
+    }
+  } catch (...) {
+    for (auto& x : th) x.join();
+    throw;
   }
-  f((int64_t)0, chunk < n ? chunk : n, 0);
+  piece((int64_t)0, chunk < n ? chunk : n, 0);
   for (auto& x : th) x.join();
+  for (auto& x : err)
+    if (x) std::rethrow_exception(x);
   return (int)parts;
 }
 constexpr int64_t kGrain = 1 << 16;
@@ -820,7 +840,11 @@ int truss_bottomup_workspace_size(int64_t cap, size_t* bytes) {
   return TRUSS_OK;
 }
 
-int truss_bottomup(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const int32_t* first_part,
+}  // extern "C"
+
+namespace {
+
+int bottomup_entry(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const int32_t* first_part,
                    int64_t cap, int32_t* truss_out, int32_t* lower_out, const truss_options* opts,
                    truss_bottomup_stats* stats, void* ws, size_t ws_bytes, void* stream) {
   const auto t0 = Clock::now();
@@ -886,6 +910,30 @@ int truss_bottomup(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
             R.st.ms_total, D.ms_relabel, D.ms_device, (long long)D.calls);
   if (stats) *stats = R.st;
   return TRUSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// The host side holds memory in proportion to the graph (its adjacency, the
+// bounds, the candidate rows) and runs host threads: a failed allocation or
+// thread start is reported as a status, never thrown across the C ABI.
+int truss_bottomup(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, const int32_t* first_part,
+                   int64_t cap, int32_t* truss_out, int32_t* lower_out, const truss_options* opts,
+                   truss_bottomup_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  try {
+    return bottomup_entry(n, m, src, dst, first_part, cap, truss_out, lower_out, opts, stats, ws, ws_bytes, stream);
+  } catch (const std::bad_alloc&) {
+    set_last_error("host memory allocation failed");
+    return TRUSS_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_last_error("host error: %s", e.what());
+    return TRUSS_E_INTERNAL;
+  } catch (...) {
+    set_last_error("host error");
+    return TRUSS_E_INTERNAL;
+  }
 }
 
 }  // extern "C"

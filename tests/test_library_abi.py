@@ -224,6 +224,34 @@ def test_binding_refuses_what_the_library_cannot_check(T):
         T.truss_bottomup(3, sn, dn[:1], 10)
 
 
+def test_bottomup_host_allocation_failure_is_a_status():
+    """The bottom-up entry holds host memory in proportion to the graph; when
+    it runs out the call returns TRUSS_E_NOMEM instead of ending the process.
+    A child process caps its address space 1 GiB above what it uses after
+    loading the library and asks for an adjacency of 400M vertices (3.2 GB of
+    offsets); the edges are validated and the adjacency built before any
+    device work, so no GPU is needed."""
+    import subprocess
+    import sys
+    code = "\n".join([
+        "import ctypes, resource, sys",
+        "sys.path.insert(0, %r)" % ROOT,
+        "import numpy as np",
+        "import paper_1205_6693_amd as T",
+        "lib = T.load_library()",
+        "s, d, out = np.array([0], np.int32), np.array([1], np.int32), np.zeros(1, np.int32)",
+        "st = T.BottomUpStats()",
+        "vm = [int(l.split()[1]) for l in open('/proc/self/status') if l.startswith('VmSize')][0] * 1024",
+        "resource.setrlimit(resource.RLIMIT_AS, (vm + (1 << 30), vm + (1 << 30)))",
+        "rc = lib.truss_bottomup(400000000, 1, s.ctypes.data, d.ctypes.data, None, 10, out.ctypes.data, None,",
+        "                        None, ctypes.byref(st), 4096, 1 << 40, None)",
+        "print('rc', rc, lib.truss_last_error().decode())",
+    ])
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "rc -9 host memory allocation failed" in r.stdout
+
+
 def test_cohen_workspace(T):
     lib = T.load_library()
     b = ctypes.c_size_t(0)
