@@ -17,6 +17,7 @@ Graph.from_csr(n, row_ptr, col) from int32/int64 CUDA tensors.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -230,10 +231,20 @@ def _ws_bytes(ws, device=None):
     return ws.numel() * ws.element_size()
 
 
-def _stream(stream):
+@contextlib.contextmanager
+def _on(device, stream=None):
+    """Makes the tensors' device current for a library call (the library
+    launches on the calling thread's current device) and yields the stream
+    handle: `stream`, else that device's current stream."""
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    dev = torch.device(device)
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        if s.device != dev:
+            raise ValueError("the stream is on %s, the tensors on %s" % (s.device, dev))
+        yield ctypes.c_void_p(s.cuda_stream)
 
 
 class Graph:
@@ -322,8 +333,9 @@ def truss_support(graph: Graph, out=None, ws=None, stream=None):
         ws = workspace(graph)
     tri = ctypes.c_int64(0)
     g = graph._c()
-    _check(lib.truss_support(ctypes.byref(g), _ptr(out), ctypes.byref(tri), _ptr(ws), _ws_bytes(ws, graph.device),
-                             _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_support(ctypes.byref(g), _ptr(out), ctypes.byref(tri), _ptr(ws), _ws_bytes(ws, graph.device),
+                                 s_))
     return out, tri.value
 
 
@@ -338,8 +350,9 @@ def truss_decompose(graph: Graph, opts: Options | None = None, out=None, ws=None
         ws = workspace(graph, opts)
     st = Stats()
     g = graph._c()
-    _check(lib.truss_decompose(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
-                               ctypes.byref(st), _ptr(ws), _ws_bytes(ws, graph.device), _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_decompose(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
+                                   ctypes.byref(st), _ptr(ws), _ws_bytes(ws, graph.device), s_))
     return out, st.to_dict()
 
 
@@ -383,9 +396,10 @@ def truss_batch(vtx_off, edge_off, src, dst, opts: Options | None = None, out=No
         ws = torch.empty(max(1, truss_batch_workspace_size(vo, eo, opts)), dtype=torch.uint8,
                          device=src.device)
     st = Stats()
-    _check(lib.truss_batch(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
-                           ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
-                           _ws_bytes(ws, src.device), _stream(stream)))
+    with _on(src.device, stream) as s_:
+        _check(lib.truss_batch(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
+                               ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
+                               _ws_bytes(ws, src.device), s_))
     return out, st.to_dict()
 
 
@@ -402,16 +416,18 @@ class BatchPlan:
         self.ws = ws if ws is not None else torch.empty(
             max(1, truss_batch_workspace_size(self.vo, self.eo, opts)), dtype=torch.uint8, device=self.src.device)
         h = ctypes.c_void_p(0)
-        _check(lib.truss_batch_plan_create(len(self.vo) - 1, self.vo.ctypes.data, self.eo.ctypes.data,
-                                           _ptr(self.src), _ptr(self.dst), _ptr(self.out),
-                                           ctypes.byref(opts) if opts else None, _ptr(self.ws),
-                                           _ws_bytes(self.ws, self.src.device),
-                                           _stream(stream), ctypes.byref(h)))
+        with _on(self.src.device, stream) as s_:
+            _check(lib.truss_batch_plan_create(len(self.vo) - 1, self.vo.ctypes.data, self.eo.ctypes.data,
+                                               _ptr(self.src), _ptr(self.dst), _ptr(self.out),
+                                               ctypes.byref(opts) if opts else None, _ptr(self.ws),
+                                               _ws_bytes(self.ws, self.src.device),
+                                               s_, ctypes.byref(h)))
         self._h = h
 
     def run(self, stream=None):
         st = Stats()
-        _check(load_library().truss_batch_plan_run(self._h, ctypes.byref(st), _stream(stream)))
+        with _on(self.src.device, stream) as s_:
+            _check(load_library().truss_batch_plan_run(self._h, ctypes.byref(st), s_))
         return self.out, st.to_dict()
 
     def close(self):
@@ -436,10 +452,11 @@ def truss_batch_autotune(vtx_off, edge_off, src, dst, opts: Options | None = Non
     if ws is None:
         ws = torch.empty(max(1, truss_batch_workspace_size(vo, eo, opts)), dtype=torch.uint8, device=src.device)
     tb, tl, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
-    _check(lib.truss_batch_autotune(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
-                                    ctypes.byref(opts) if opts else None, _ptr(ws), _ws_bytes(ws, src.device),
-                                    _stream(stream),
-                                    ctypes.byref(tb), ctypes.byref(tl), ctypes.byref(ms)))
+    with _on(src.device, stream) as s_:
+        _check(lib.truss_batch_autotune(len(vo) - 1, vo.ctypes.data, eo.ctypes.data, _ptr(src), _ptr(dst), _ptr(out),
+                                        ctypes.byref(opts) if opts else None, _ptr(ws), _ws_bytes(ws, src.device),
+                                        s_,
+                                        ctypes.byref(tb), ctypes.byref(tl), ctypes.byref(ms)))
     return tb.value, tl.value, ms.value
 
 
@@ -463,9 +480,10 @@ def truss_decompose_traced(graph: Graph, opts: Options | None = None, level_cap:
     tr.level_feat, tr.level_ms, tr.level_action = _ptr(feat).value, _ptr(lms).value, _ptr(lact).value
     st = Stats()
     g = graph._c()
-    _check(lib.truss_decompose_traced(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
-                                      ctypes.byref(st), ctypes.byref(tr), _ptr(ws), _ws_bytes(ws, graph.device),
-                                      _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_decompose_traced(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
+                                          ctypes.byref(st), ctypes.byref(tr), _ptr(ws), _ws_bytes(ws, graph.device),
+                                          s_))
     L = tr.levels
     trace = {"levels": L,
              "level_feat": feat[:L].cpu().numpy(),
@@ -506,8 +524,9 @@ def mlp_forward(params, X, H: int, O: int, stream=None):
     _dev(params, "params", torch.float32, mlp_param_count(F, H, O), X.device)
     Y = torch.empty((B, O), dtype=torch.float32, device=X.device)
     ws = _mlp_ws(F, H, O, B, X.device)
-    _check(load_library().truss_mlp_forward(_ptr(params), F, H, O, _ptr(X), B, _ptr(Y), _ptr(ws), _ws_bytes(ws),
-                                            _stream(stream)))
+    with _on(X.device, stream) as s_:
+        _check(load_library().truss_mlp_forward(_ptr(params), F, H, O, _ptr(X), B, _ptr(Y), _ptr(ws), _ws_bytes(ws),
+                                                s_))
     return Y
 
 
@@ -524,8 +543,9 @@ def mlp_backward(params, X, dY, H: int, stream=None):
     _dev(params, "params", torch.float32, mlp_param_count(F, H, O), X.device)
     grad = torch.empty(params.numel(), dtype=torch.float32, device=X.device)
     ws = _mlp_ws(F, H, O, B, X.device)
-    _check(load_library().truss_mlp_backward(_ptr(params), F, H, O, _ptr(X), B, _ptr(dY), _ptr(grad), _ptr(ws),
-                                             _ws_bytes(ws), _stream(stream)))
+    with _on(X.device, stream) as s_:
+        _check(load_library().truss_mlp_backward(_ptr(params), F, H, O, _ptr(X), B, _ptr(dY), _ptr(grad), _ptr(ws),
+                                                 _ws_bytes(ws), s_))
     return grad
 
 
@@ -547,9 +567,10 @@ def mlp_train(params, adam_m, adam_v, X, T, Wt, H: int, steps: int, step0: int =
         _dev(t, name, torch.float32, P, X.device)  # updated in place
     ws = _mlp_ws(F, H, O, B, X.device)
     loss = ctypes.c_float(0.0)
-    _check(load_library().truss_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), F, H, O, _ptr(X), _ptr(T),
-                                          _ptr(Wt), B, steps, step0, lr, ctypes.byref(loss), _ptr(ws),
-                                          _ws_bytes(ws), _stream(stream)))
+    with _on(X.device, stream) as s_:
+        _check(load_library().truss_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), F, H, O, _ptr(X), _ptr(T),
+                                              _ptr(Wt), B, steps, step0, lr, ctypes.byref(loss), _ptr(ws),
+                                              _ws_bytes(ws), s_))
     return loss.value
 
 
@@ -581,8 +602,9 @@ def sched_train(kind: int, X, T_ms, H: int = 32, steps: int = 3000, lr: float = 
     _check(lib.truss_sched_train_workspace_size(kind, H, B, ctypes.byref(b)))
     ws = torch.empty(b.value, dtype=torch.uint8, device=X.device)
     loss = ctypes.c_float(0.0)
-    _check(lib.truss_sched_train(kind, _ptr(X), _ptr(T_ms), B, H, steps, lr, seed, _ptr(out),
-                                 ctypes.byref(loss), _ptr(ws), _ws_bytes(ws), _stream(stream)))
+    with _on(X.device, stream) as s_:
+        _check(lib.truss_sched_train(kind, _ptr(X), _ptr(T_ms), B, H, steps, lr, seed, _ptr(out),
+                                     ctypes.byref(loss), _ptr(ws), _ws_bytes(ws), s_))
     return out, loss.value
 
 
@@ -596,8 +618,9 @@ def truss_upper_bound(graph: Graph, out=None, ws=None, stream=None):
     if ws is None:
         ws = workspace(graph)
     g = graph._c()
-    _check(lib.truss_upper_bound(ctypes.byref(g), _ptr(out), _ptr(ws), _ws_bytes(ws, graph.device),
-                                 _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_upper_bound(ctypes.byref(g), _ptr(out), _ptr(ws), _ws_bytes(ws, graph.device),
+                                     s_))
     return out
 
 
@@ -616,9 +639,10 @@ def truss_topdown(graph: Graph, t: int, opts: Options | None = None, out=None, w
         ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
     kmin, kmax = ctypes.c_int32(0), ctypes.c_int32(0)
     st = Stats()
-    _check(lib.truss_topdown(ctypes.byref(g), t, _ptr(out), ctypes.byref(kmin), ctypes.byref(kmax),
-                             ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
-                             _ws_bytes(ws, graph.device), _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_topdown(ctypes.byref(g), t, _ptr(out), ctypes.byref(kmin), ctypes.byref(kmax),
+                                 ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
+                                 _ws_bytes(ws, graph.device), s_))
     return out, kmin.value, kmax.value, st.to_dict()
 
 
@@ -636,8 +660,9 @@ def truss_core_numbers(graph: Graph, out=None, ws=None, stream=None):
         _check(lib.truss_core_workspace_size(ctypes.byref(g), ctypes.byref(b)))
         ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
     cmax = ctypes.c_int32(0)
-    _check(lib.truss_core_numbers(ctypes.byref(g), _ptr(out), ctypes.byref(cmax), _ptr(ws),
-                                  _ws_bytes(ws, graph.device), _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_core_numbers(ctypes.byref(g), _ptr(out), ctypes.byref(cmax), _ptr(ws),
+                                      _ws_bytes(ws, graph.device), s_))
     return out[:graph.n], cmax.value
 
 
@@ -652,8 +677,9 @@ def truss_cohesion(graph: Graph, opts: Options | None = None, ws=None, stream=No
         _check(lib.truss_cohesion_workspace_size(ctypes.byref(g), ctypes.byref(b)))
         ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
     st = CohesionStats()
-    _check(lib.truss_cohesion(ctypes.byref(g), ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
-                              _ws_bytes(ws, graph.device), _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_cohesion(ctypes.byref(g), ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws),
+                                  _ws_bytes(ws, graph.device), s_))
     return st.to_dict()
 
 
@@ -682,10 +708,11 @@ def truss_bottomup(n: int, src, dst, cap: int, first_part=None, opts: Options | 
     out = np.zeros(max(m, 1), dtype=np.int32)
     low = np.zeros(max(m, 1), dtype=np.int32)
     st = BottomUpStats()
-    _check(lib.truss_bottomup(int(n), m, src.ctypes.data, dst.ctypes.data,
-                              None if fp is None else fp.ctypes.data, int(cap), out.ctypes.data, low.ctypes.data,
-                              ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), _ws_bytes(ws),
-                              _stream(stream)))
+    with _on(ws.device, stream) as s_:
+        _check(lib.truss_bottomup(int(n), m, src.ctypes.data, dst.ctypes.data,
+                                  None if fp is None else fp.ctypes.data, int(cap), out.ctypes.data, low.ctypes.data,
+                                  ctypes.byref(opts) if opts else None, ctypes.byref(st), _ptr(ws), _ws_bytes(ws),
+                                  s_))
     return out[:m], low[:m], st.to_dict()
 
 
@@ -704,6 +731,7 @@ def truss_cohen(graph: Graph, out=None, ws=None, stream=None):
         _check(lib.truss_cohen_workspace_size(ctypes.byref(g), ctypes.byref(b)))
         ws = torch.empty(max(1, b.value), dtype=torch.uint8, device=graph.device)
     st = Stats()
-    _check(lib.truss_cohen(ctypes.byref(g), _ptr(out), ctypes.byref(st), _ptr(ws), _ws_bytes(ws, graph.device),
-                           _stream(stream)))
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_cohen(ctypes.byref(g), _ptr(out), ctypes.byref(st), _ptr(ws), _ws_bytes(ws, graph.device),
+                               s_))
     return out, st.to_dict()
