@@ -11,9 +11,17 @@ Entry points mirror the C ABI in include/truss.h:
     truss_decompose_traced(graph, ...) -> (truss, stats, trace dict)
     truss_upper_bound(graph)          -> psi int32[m] (Procedure 6)
     truss_topdown(graph, t)           -> (top-t classes int32[m], kmin, kmax, stats)
+    truss_core_numbers(graph)         -> (core int32[n] cuda tensor, c_max)
+    truss_cohesion(graph)             -> Table 6's statistics (dict)
+    truss_bottomup(n, src, dst, cap)  -> (truss, lower bound, stats) for a graph in
+                                         host memory (numpy int32 arrays)
+    truss_cohen(graph)                -> (truss int32[m], stats) by Algorithm 1
+    BatchPlan / truss_batch_autotune  -> a replayable batch and its shape
     mlp_forward / mlp_backward / mlp_train / sched_train -> the scheduler network
 Graphs are built with Graph.from_edges(n, src, dst) or
-Graph.from_csr(n, row_ptr, col) from int32/int64 CUDA tensors.
+Graph.from_csr(n, row_ptr, col) from int32/int64 CUDA tensors.  Tensors are
+checked (device, dtype, contiguity, length) before each call, which runs with
+their device current and, unless a stream is given, on its current stream.
 """
 from __future__ import annotations
 
