@@ -4,9 +4,12 @@
 A step is one truss_decompose call on the resident input graph: validation,
 CSR build, support counting, peeling, output.  Inputs are generated on the host
 from a seed and copied to HBM before the timed region; the timed region covers
-exactly K steps bracketed by device synchronisation.  The headline value is the
-learned-scheduled form (the committed model); the plain and heuristic forms
-are timed the same way afterwards for comparison.
+exactly K steps bracketed by device synchronisation.  The default workload is
+R-MAT scale 24 (260M edges, CSR).  The headline value is the learned-scheduled
+form (the committed model); the plain and heuristic forms are timed afterwards
+with fewer steps (--compare-steps) for comparison.  The output of the last
+timed step is hashed and compared with the oracle's stored digest for the
+workload ("verified" in the JSON line).
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (measured with HIP events on the library's stream) and the CPU oracle timed on a
@@ -71,6 +74,62 @@ def host_work_model(n, row_ptr, col):
     return {"support_pairs": pairs, "oriented_edges": int(before.sum()), "max_outdeg": int(dplus.max(initial=0)),
             "merge_elems": int((dplus * dplus).sum()) + pairs, "sum_min_deg": int(mn.sum()),
             "sum_min_deg_log": int((mn * lg).sum())}
+
+
+def device_work_model(n, row_ptr, col):
+    """host_work_model's counts computed with torch on the GPU (the same
+    formulas; R-MAT 24's 520M row entries take seconds there, minutes in
+    numpy).  row_ptr, col: the CSR tensors on the device."""
+    import torch
+    deg = row_ptr[1:] - row_ptr[:-1]
+    rows = torch.repeat_interleave(torch.arange(n, device=col.device, dtype=torch.int64), deg)
+    c = col.to(torch.int64)
+    dr, dc = deg[rows], deg[c]
+    before = (dr < dc) | ((dr == dc) & (rows < c))
+    dplus = torch.bincount(rows[before], minlength=n).to(torch.int64)
+    pairs = int(dplus[c[before]].sum().item())
+    oriented = int(before.sum().item())
+    del before
+    upper = rows < c
+    du, dv = dr[upper], dc[upper]
+    del rows, c, dr, dc, upper
+    mn, mx = torch.minimum(du, dv), torch.maximum(du, dv)
+    del du, dv
+    lg = torch.ceil(torch.log2(mx.clamp(min=1).to(torch.float64))).to(torch.int64)
+    out = {"support_pairs": pairs, "oriented_edges": oriented, "max_outdeg": int(dplus.max().item()) if n else 0,
+           "merge_elems": int((dplus * dplus).sum().item()) + pairs, "sum_min_deg": int(mn.sum().item()),
+           "sum_min_deg_log": int((mn * lg).sum().item())}
+    del mn, mx, lg
+    if col.is_cuda:
+        torch.cuda.empty_cache()
+    return out
+
+
+def verify_output(workload, out_host, order=None):
+    """Compares the truss numbers of a timed step with the oracle's stored
+    record for the workload (tests/golden/oracle_<workload>.txt: SHA-256 of the
+    int32 truss numbers in canonical edge order, written from the oracle
+    alone).  order: index array that puts out_host into canonical order (None:
+    already canonical).  Truss numbers are unique (Definition 2), so the
+    comparison is exact.  Returns (verified or None when no record exists,
+    the record's oracle seconds or None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "tests", "golden", "oracle_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None, None
+    want, secs = None, None
+    for line in open(path):
+        if line.startswith("truss_sha256:"):
+            want = line.split(":", 1)[1].strip()
+        mt = re.search(r"\((\d+) s on one core\)", line)
+        if mt and secs is None:
+            secs = int(mt.group(1))
+    if want is None:
+        return None, secs
+    a = out_host if order is None else out_host[order]
+    got = hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+    return got == want, secs
 
 
 def edge_work_model(n, s, d):
@@ -156,11 +215,44 @@ def calibrate_copy(nbytes):
                       "dispatches": 5}))
 
 
+def _short(name):
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("truss::", "")
+    return name.split("(")[0] if "(" in name else name
+
+
+def summarize_db(path):
+    """Kernel durations (and PMC counters, when the run collected them) from a
+    rocprofv3 SQLite output file."""
+    import sqlite3
+    out = []
+    c = sqlite3.connect(path)
+    rows = c.execute("select name, count(*), sum(duration), avg(duration) from kernels group by name "
+                     "order by sum(duration) desc").fetchall()
+    out.append("kernel stats: " + os.path.basename(path))
+    for name, calls, tot, avg in rows:
+        out.append("  %-60s calls=%d total_ns=%d avg_ns=%.0f" % (_short(name)[:60], calls, tot, avg))
+    try:
+        cnt = c.execute("select k.name, p.counter_name, count(distinct p.dispatch_id), sum(p.value) "
+                        "from counters_collection p join kernels k on k.dispatch_id = p.dispatch_id "
+                        "group by k.name, p.counter_name").fetchall()
+    except sqlite3.Error:
+        cnt = []
+    if cnt:
+        out.append("counters: " + os.path.basename(path))
+        for name, cname, disp, val in cnt:
+            out.append("  %-50s %-12s dispatches=%d total=%.6g per_dispatch=%.6g"
+                       % (_short(name)[-50:], cname, disp, val, val / max(1, disp)))
+    return out
+
+
 def summarize(prof_dir):
-    """Text summary of rocprofv3 CSV output (kernel stats and counters)."""
+    """Text summary of rocprofv3 output (kernel stats and counters), CSV or
+    SQLite."""
     import csv
     import glob
     out = []
+    for f in sorted(glob.glob(os.path.join(prof_dir, "**", "*.db"), recursive=True)):
+        out.extend(summarize_db(f))
     for f in sorted(glob.glob(os.path.join(prof_dir, "**", "*kernel_stats.csv"), recursive=True)):
         out.append("kernel stats: " + os.path.relpath(f, prof_dir))
         for r in csv.DictReader(open(f)):
@@ -335,7 +427,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
+    ap.add_argument("--compare-steps", type=int, default=3,
+                    help="timed steps of each comparison form (after one warm-up step)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--scheduler", default="learned", choices=["plain", "heuristic", "learned"])
     ap.add_argument("--no-compare", action="store_true", help="skip timing the other scheduler forms")
@@ -385,15 +479,19 @@ def main():
     import graphgen
     m = s.size
     model = None
+    canon_order = None  # puts the output into canonical edge order
     if fmt == "csr":
         row_ptr, col = graphgen.to_csr(n, s, d)
         g = T.Graph.from_csr(n, torch.from_numpy(row_ptr).cuda(), torch.from_numpy(col).cuda())
-        model = host_work_model(n, row_ptr, col)
+        del row_ptr, col
+        model = device_work_model(n, g.row_ptr, g.col)
         host_edges = (s, d)  # canonical order = the CSR output order
     else:
         s2, d2 = graphgen.shuffle(s, d, 12345)
         g = T.Graph.from_edges(n, torch.from_numpy(s2).cuda(), torch.from_numpy(d2).cuda())
         host_edges = (s2, d2)
+        lo, hi = np.minimum(s2, d2).astype(np.int64), np.maximum(s2, d2).astype(np.int64)
+        canon_order = np.lexsort((hi, lo))
         row_ptr, col = graphgen.to_csr(n, s, d)
         model = host_work_model(n, row_ptr, col)
     sched_ids = {"plain": T.SCHED_PLAIN, "heuristic": T.SCHED_HEURISTIC, "learned": T.SCHED_LEARNED}
@@ -432,6 +530,8 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     print("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step), file=sys.stderr, flush=True)
+    verified, oracle_secs = verify_output(args.workload, out.cpu().numpy(), canon_order)
+    print("output of the last timed step equals the oracle record: %s" % verified, file=sys.stderr, flush=True)
 
     def avg(key):
         return float(np.mean([x[key] for x in stats]))
@@ -476,6 +576,7 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "seed": args.seed,
                    "n": n, "m": m, "scheduler": args.scheduler, "probe": args.probe,
                    "peel_mode": args.peel_mode, "support": args.support},
+        "verified": verified,
         "phases_ms": {"build": ms_build, "support": ms_sup, "peel": ms_peel},
         "kmax": st["kmax"], "levels": st["levels"], "subrounds": st["subrounds"],
         "triangles": st["triangles"], "peel_work": st["peel_work"], "launches": st["launches"],
@@ -487,22 +588,25 @@ def main():
                              "walked_bytes": v["walked"]} for k, v in kernels.items()},
         "peel_kernel_ms": ms_peel_kernel,
     }
-    forms = {args.scheduler: {"edges_per_s": result["value"], "ms_per_step": ms_per_step}}
+    forms = {args.scheduler: {"edges_per_s": result["value"], "ms_per_step": ms_per_step, "steps": args.steps,
+                              "warmup": args.warmup, "verified": verified}}
     if not args.no_compare:
         for name in ("plain", "heuristic", "learned"):
             if name in forms:
                 continue
             o = form_options(name)
-            for _ in range(args.warmup):
-                T.truss_decompose(g, o, out=out, ws=ws)
+            T.truss_decompose(g, o, out=out, ws=ws)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            for _ in range(args.steps):
+            for _ in range(args.compare_steps):
                 T.truss_decompose(g, o, out=out, ws=ws)
             torch.cuda.synchronize()
-            ms = (time.perf_counter() - t1) * 1e3 / args.steps
-            forms[name] = {"edges_per_s": m / (ms * 1e-3), "ms_per_step": ms}
-            print("form %s: %.3f ms/step" % (name, ms), file=sys.stderr, flush=True)
+            ms = (time.perf_counter() - t1) * 1e3 / args.compare_steps
+            ok, _ = verify_output(args.workload, out.cpu().numpy(), canon_order)
+            forms[name] = {"edges_per_s": m / (ms * 1e-3), "ms_per_step": ms, "steps": args.compare_steps,
+                           "warmup": 1, "verified": ok}
+            print("form %s: %.3f ms/step (output equals the oracle record: %s)" % (name, ms, ok),
+                  file=sys.stderr, flush=True)
     result["forms"] = forms
     if "plain" in forms and "learned" in forms:
         result["learned_over_plain"] = forms["learned"]["edges_per_s"] / forms["plain"]["edges_per_s"]
@@ -537,6 +641,11 @@ def main():
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale, args.seed)
+        if oracle_secs:
+            result["cpu_baseline"]["recorded_full_size"] = {
+                "workload": args.workload, "seconds": oracle_secs, "edges_per_s": m / oracle_secs, "cores": 1,
+                "note": "the oracle on the whole workload graph (support + Algorithm 2), timed once when its "
+                        "stored digests were written, on the build host's CPU, not this one"}
     print(json.dumps(result), flush=True)
 
 

@@ -118,7 +118,12 @@ typedef struct truss_options {
   int32_t peel_probe;       /* TRUSS_PROBE_*                                    */
   int32_t batch_block;      /* truss_batch: threads per workgroup (256, 512, 1024; 0 = 1024) */
   int32_t batch_ilp;        /* truss_batch: walk entries in flight per thread (1, 2, 4; 0 = 2) */
-  int32_t reserved[4];
+  int32_t model_floats;     /* floats readable at *model; > 0: a model whose two
+                               part headers ask for more (or for a different
+                               total) is rejected like a malformed one (the
+                               heuristic runs, sched_fallback = 1); 0: the
+                               caller vouches for the length              */
+  int32_t reserved[3];
 } truss_options;
 
 /* Filled when a stats pointer is passed (host). */

@@ -62,7 +62,7 @@ class Options(ctypes.Structure):
                 ("model", ctypes.c_void_p), ("max_subrounds", ctypes.c_int64),
                 ("grid_blocks", ctypes.c_int32), ("peel_probe", ctypes.c_int32),
                 ("batch_block", ctypes.c_int32), ("batch_ilp", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("model_floats", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -312,6 +312,8 @@ def make_options(support_strategy=SUP_AUTO, peel_mode=PEEL_AUTO, scheduler=SCHED
     if model is not None:
         _dev(model, "model", _torch().float32, 4)
         o._model = model  # the options hold its address: keep it alive with them
+        # the library reads no float past this count (a truncated model falls back)
+        o.model_floats = min(model.numel(), 0x7fffffff)
     o.model = _ptr(model).value if model is not None else None
     o.max_subrounds, o.grid_blocks = max_subrounds, grid_blocks
     return o

@@ -98,9 +98,14 @@ int validate_options(const truss_options* o) {
 namespace {
 
 // Checks a learned model's two part headers (device memory) against the
-// network shapes the scheduler evaluates; fills the part pointers.
-bool model_parts(const float* model, const float** peel_part, const float** sup_part, hipStream_t s) {
+// network shapes the scheduler evaluates and, when the caller states how many
+// floats the model holds (nfloats > 0), against that length: both headers
+// must lie inside it and the two parts must fill it exactly.  Fills the part
+// pointers.
+bool model_parts(const float* model, int64_t nfloats, const float** peel_part, const float** sup_part,
+                 hipStream_t s) {
   if (!model) return false;
+  if (nfloats > 0 && nfloats < 4) return false;
   float h[4];
   if (hipMemcpyAsync(h, model, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
   if (hipStreamSynchronize(s) != hipSuccess) return false;
@@ -108,12 +113,14 @@ bool model_parts(const float* model, const float** peel_part, const float** sup_
       !(h[2] <= (float)kMlpMaxH) || h[2] != (float)(int)h[2])
     return false;
   const int off = model_part_floats(kPeelF, (int)h[2], kPeelA);
+  if (nfloats > 0 && (int64_t)off + 4 > nfloats) return false;
   float g[4];
   if (hipMemcpyAsync(g, model + off, sizeof(g), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
   if (hipStreamSynchronize(s) != hipSuccess) return false;
   if (g[0] != kModelTag || g[1] != (float)kSupF || g[3] != (float)kSupA || !(g[2] >= 1.f) ||
       !(g[2] <= (float)kMlpMaxH) || g[2] != (float)(int)g[2])
     return false;
+  if (nfloats > 0 && (int64_t)off + model_part_floats(kSupF, (int)g[2], kSupA) != nfloats) return false;
   *peel_part = model;
   *sup_part = model + off;
   return true;
@@ -128,7 +135,7 @@ void resolve(const truss_options* in, SupPlan* sp, PeelPlan* pp, int* fallback, 
   *fallback = 0;
   int sched = o.scheduler;
   const float *peel_part = nullptr, *sup_part = nullptr;
-  if (sched == TRUSS_SCHED_LEARNED && !model_parts(o.model, &peel_part, &sup_part, s)) {
+  if (sched == TRUSS_SCHED_LEARNED && !model_parts(o.model, o.model_floats, &peel_part, &sup_part, s)) {
     *fallback = 1;
     sched = TRUSS_SCHED_HEURISTIC;
   }

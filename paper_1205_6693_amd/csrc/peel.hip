@@ -18,8 +18,14 @@
 // search.  Deleted edges are only marked (Section 3.1); the rows are compacted
 // in place whenever the live edge count has halved.
 //
-// The level loop runs in a persistent cooperative kernel, one 1024-thread
-// workgroup per compute unit.  Phases are separated by a grid barrier; the last
+// The level loop runs in a persistent kernel, one 1024-thread workgroup per
+// compute unit.  The grid is never larger than the number of workgroups the
+// device holds at once (one per compute unit, checked against the occupancy
+// of the kernel before the first launch), so every workgroup is resident and
+// the grid barrier can complete; the launch is an ordinary one on the
+// caller's stream (a cooperative launch goes through a queue of its own,
+// which profilers tear down at exit after the run's results are written, and
+// adds nothing here).  Phases are separated by a grid barrier; the last
 // workgroup to arrive runs the control step (next phase, next level
 // k = max(k+1, min live support + 2), queue sizes) before releasing the others.
 // The kernel returns to the host only to compact the rows (a separate kernel)
@@ -1132,7 +1138,6 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
   P.tr_feat = P.tr_cap > 0 ? trace->level_feat : nullptr;
   P.tr_ms = P.tr_cap > 0 ? trace->level_ms : nullptr;
   P.tr_act = P.tr_cap > 0 ? trace->level_action : nullptr;
-  void* args[] = {&P};
   PeelCtl h;
   int launches = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1140,7 +1145,8 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
   double kernel_ms = 0.0;
   for (;;) {
     if (timed) (void)hipEventRecord(ev0, s);
-    TRUSS_HIP(hipLaunchCooperativeKernel((const void*)k_peel, dim3(blocks), dim3(kT), args, 0, s));
+    hipLaunchKernelGGL(k_peel, dim3(blocks), dim3(kT), 0, s, P);
+    TRUSS_HIP(hipGetLastError());
     if (timed) (void)hipEventRecord(ev1, s);
     ++launches;
     TRUSS_HIP(hipMemcpyAsync(&h, L.ctl, sizeof(PeelCtl), hipMemcpyDeviceToHost, s));

@@ -94,3 +94,36 @@ def test_digest_ignores_comments_only(tmp_path, monkeypatch):
     peel.write_text(text.replace("kMinChunk = 64", "kMinChunk = 32"))
     assert bench.source_digest("k_peel") != base
     assert bench.source_digest("k_batch") == batch  # the batch kernel does not depend on peel.hip
+
+
+def test_device_work_model_matches_host_model():
+    """The torch form of the counts (run on the GPU at full size) equals the
+    numpy form; here both run on the CPU."""
+    import torch
+    for scale, ef, seed in ((10, 8, 1), (12, 16, 2)):
+        n, s, d = graphgen.rmat(scale, ef, seed)
+        rp, col = graphgen.to_csr(n, s, d)
+        h = bench.host_work_model(n, rp, col)
+        t = bench.device_work_model(n, torch.from_numpy(rp), torch.from_numpy(col))
+        for k in ("support_pairs", "oriented_edges", "max_outdeg", "merge_elems", "sum_min_deg", "sum_min_deg_log"):
+            assert h[k] == t[k], k
+
+
+def test_verify_output_against_the_stored_record():
+    """bench.py's check of a timed output: the oracle's own truss numbers of
+    the ER workload match the stored digest, in canonical order and through a
+    shuffle's ordering; a single changed value does not."""
+    import oracle
+    n, s, d = graphgen.er_small(1)
+    phi, _ = oracle.truss(n, s, d)
+    ok, secs = bench.verify_output("er2000", phi)
+    assert ok is True
+    bad = phi.copy()
+    bad[17] += 1
+    assert bench.verify_output("er2000", bad)[0] is False
+    s2, d2 = graphgen.shuffle(s, d, 12345)
+    phi2, _ = oracle.truss(n, s2, d2)
+    lo, hi = np.minimum(s2, d2).astype(np.int64), np.maximum(s2, d2).astype(np.int64)
+    assert bench.verify_output("er2000", phi2, np.lexsort((hi, lo)))[0] is True
+    assert bench.verify_output("no_such_workload", phi) == (None, None)
+    assert bench.verify_output("rmat24", phi)[1] == 11210

@@ -13,7 +13,7 @@ import pytest
 
 import golden_io
 import graphgen
-from gpu_util import csr_graph, gpu_support, gpu_truss, say
+from gpu_util import csr_graph, gpu_support, gpu_truss, lib, say
 
 pytestmark = pytest.mark.gpu
 
@@ -26,8 +26,17 @@ WORKLOADS = {
 }
 
 # scheduler 0 = plain (merge support, dense frontier, bsearch probes),
-# 1 = fixed heuristic (the default)
-SCHEDULERS = [dict(), dict(scheduler=0)]
+# 1 = fixed heuristic (the default), 2 = learned with the committed model (the
+# form the benchmark times, in its launch configuration)
+SCHEDULERS = [dict(), dict(scheduler=0), "learned"]
+
+
+def _options(opt):
+    if opt == "learned":
+        from paper_1205_6693_amd import sched
+        T = lib()
+        return dict(scheduler=T.SCHED_LEARNED, model=sched.load_model())
+    return opt
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
@@ -45,7 +54,9 @@ def test_fullsize_digest(name):
     assert golden_io.int32_digest(sup) == rec["support_sha256"]
     for opt in SCHEDULERS:
         say(f"  options {opt}")
-        phi, st = gpu_truss(g, **opt)
+        phi, st = gpu_truss(g, **_options(opt))
+        if opt == "learned":
+            assert st["sched_fallback"] == 0
         hist = np.bincount(phi, minlength=rec["kmax"] + 1)
         got = {k: int(c) for k, c in enumerate(hist) if c}
         assert st["kmax"] == rec["kmax"]

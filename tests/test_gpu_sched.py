@@ -147,8 +147,12 @@ def test_malformed_model_falls_back():
     n, s, d = graphgen.er_small(3)
     ref, _ = oracle.truss(n, s, d)
     bad = _random_model(1)
+    good = bad.copy()
     bad[0] = 7.0
-    for model in (None, dev(bad)):
+    # valid headers but fewer floats than they ask for: the binding passes the
+    # tensor's length and the library must not read past it
+    truncated = (good[:4].copy(), good[:-1].copy(), np.concatenate([good, np.zeros(3, good.dtype)]))
+    for model in (None, dev(bad)) + tuple(dev(t) for t in truncated):
         o = T.make_options(scheduler=T.SCHED_LEARNED, model=model)
         out, st = T.truss_decompose(edges_graph(n, s, d), o)
         assert st["sched_fallback"] == 1
