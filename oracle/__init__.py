@@ -5,9 +5,9 @@ leg of the benchmark use it; the GPU library never imports, links or calls it.
 
 Functions follow Wang & Cheng, "Truss Decomposition in Massive Networks":
   validate_edges / validate_csr  -- Section 2 (simple undirected graphs)
-  support_def                    -- Definition 1 via Algorithm 1, Steps 2-3
+  support_def                    -- Definition 1 via the support merge of Algorithm 1
   support_fwd                    -- Definition 1 via the triangle counting that
-                                    Algorithm 2, Step 2 cites (Section 3.2)
+                                    Algorithm 2 starts from (Section 3.2)
   truss                          -- Definition 2 / truss number via Algorithm 2
   upper_bound                    -- psi(e) of Procedure 6 (Lemma 2: phi <= psi)
   top_classes                    -- the top-t k-classes of Algorithm 7 from phi

@@ -12,10 +12,10 @@
  *   - sup(e), the number of triangles containing e (Definition 1), by two
  *     independent routines:
  *       (i)  oracle_support_def: |nb(u) ∩ nb(v)| for every edge by a two-pointer
- *            merge of the full sorted adjacency lists (Algorithm 1, Steps 2-3);
+ *            merge of the full sorted adjacency lists (the support of Algorithm 1);
  *       (ii) oracle_support_fwd: every triangle listed once through the
  *            degree orientation (deg, id) and counted on its three edges — the
- *            in-memory triangle counting cited for Algorithm 2, Step 2
+ *            in-memory triangle counting Algorithm 2 starts from
  *            (Section 3.2);
  *   - phi(e), the truss number (Definition 2 and the text after it), by
  *     Algorithm 2 (Section 3.2): bin sort of edges by support, then repeatedly
@@ -24,13 +24,14 @@
  *     decrement (u,w) and (v,w) and re-bin them; e joins the k-class.
  *
  * Readings where the paper is silent (each is listed in the design notes):
- *   - Algorithm 2, Step 9 decrements unconditionally.  Here an edge whose
+ *   - Algorithm 2 decrements the two other edges unconditionally.  Here an edge whose
  *     support is already <= k-2 is not decremented: it is removed at this level
  *     anyway (so its truss number is k either way) and the guard keeps the bin
  *     array sorted without moving an edge left of the pointer.
  *   - "w in nb(u)" and "(v,w) in E_G" are read on the current graph: both
  *     (u,w) and (v,w) must not have been removed yet.
- *   - deg() in Step 6 is the original degree; ties go to the smaller id.
+ *   - The endpoint whose neighbours are walked is chosen by original degree;
+ *     ties go to the smaller id.
  *   - Edge identity: edge i is the i-th input pair; outputs are per input pair.
  *
  * Error codes are returned as negative numbers; when several violations exist
@@ -207,7 +208,7 @@ int oracle_csr_to_edges(int32_t n, int64_t m, const int64_t *row_ptr, const int3
 /* ------------------------------------------------------------------------- */
 
 /* (i) |nb(u) ∩ nb(v)| for every edge, by merging the two full sorted lists
- * (Algorithm 1, Step 3).  O(sum_v deg(v)^2). */
+ * (the support computation of Algorithm 1).  O(sum_v deg(v)^2). */
 int oracle_support_def(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                        int32_t *sup, int64_t *triangles) {
   adj_t g;
@@ -296,82 +297,106 @@ static int64_t find_nbr(const adj_t *g, int32_t v, int32_t w) {
   return (lo < g->off[v + 1] && g->nbr[lo] == w) ? lo : -1;
 }
 
-/* phi[i] for every input edge i; kmax_out (nullable) gets the largest phi
- * (2 for an edgeless graph is not reported: kmax_out = 0 when m = 0). */
+/* Edges kept sorted by current support (the bin sort of Algorithm 2):
+ * order[] lists the edges by support, pos[e] is e's place in it and start[s]
+ * the first place holding support s.  Lowering an edge's support by one swaps
+ * it with the first edge of its bin and moves that bin's start past it, so
+ * order[] stays sorted. */
+typedef struct {
+  int64_t *order, *pos, *start;
+  int32_t *sup;
+} bins_t;
+
+static void bins_free(bins_t *b) {
+  free(b->order); free(b->pos); free(b->start);
+  memset(b, 0, sizeof(*b));
+}
+
+static int bins_build(int64_t m, int32_t *sup, bins_t *b) {
+  int32_t maxsup = 0;
+  for (int64_t i = 0; i < m; ++i) if (sup[i] > maxsup) maxsup = sup[i];
+  b->sup = sup;
+  b->start = (int64_t *)calloc((size_t)maxsup + 2, sizeof(int64_t));
+  b->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+  b->pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)maxsup + 1));
+  if (!b->start || !b->order || !b->pos || !fill) { free(fill); bins_free(b); return -OR_NOMEM; }
+  for (int64_t i = 0; i < m; ++i) b->start[sup[i] + 1]++;
+  for (int32_t s = 0; s <= maxsup; ++s) b->start[s + 1] += b->start[s];
+  for (int32_t s = 0; s <= maxsup; ++s) fill[s] = b->start[s];
+  for (int64_t i = 0; i < m; ++i) { b->pos[i] = fill[sup[i]]++; b->order[b->pos[i]] = i; }
+  free(fill);
+  return OR_OK;
+}
+
+static void bins_lower(bins_t *b, int64_t f) {
+  const int32_t s = b->sup[f];
+  const int64_t here = b->pos[f], first = b->start[s];
+  const int64_t other = b->order[first];
+  b->order[first] = f; b->pos[f] = first;
+  b->order[here] = other; b->pos[other] = here;
+  b->start[s]++;
+  b->sup[f] = s - 1;
+}
+
+/* Removes e = (u, v) at level k: every triangle (u, v, w) whose other two
+ * edges are still present loses e, so each of those edges loses one support
+ * -- unless its support is already at most k - 2 (it leaves at this level
+ * whatever happens; the guard keeps it from moving before the current
+ * position of the bin order).  The triangles are found from the endpoint
+ * that comes first in (degree, id) order, each w looked up in the other's
+ * sorted list (Section 3.2's choice of the smaller-degree endpoint). */
+static void remove_edge(const adj_t *g, bins_t *b, unsigned char *removed, const int32_t *src,
+                        const int32_t *dst, int64_t e, int32_t k) {
+  int32_t near = src[e], far = dst[e];
+  if (!before(g, near, far)) { int32_t t = near; near = far; far = t; }
+  for (int64_t j = g->off[near]; j < g->off[near + 1]; ++j) {
+    const int32_t w = g->nbr[j];
+    const int64_t e1 = g->eid[j];
+    if (w == far || removed[e1]) continue;
+    const int64_t q = find_nbr(g, far, w);
+    if (q < 0 || removed[g->eid[q]]) continue;
+    const int64_t e2 = g->eid[q];
+    if (b->sup[e1] > k - 2) bins_lower(b, e1);
+    if (b->sup[e2] > k - 2) bins_lower(b, e2);
+  }
+  removed[e] = 1;
+}
+
+/* Truss numbers by Algorithm 2 (Section 3.2): supports from triangle
+ * counting, edges in bin order, and a level k that rises whenever the next
+ * edge in that order has support above k - 2; an edge taken at level k has
+ * truss number k.  phi[i] for every input edge i; kmax_out (nullable) gets
+ * the largest phi (0 when m = 0). */
 int oracle_truss(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                  int32_t *phi, int32_t *kmax_out) {
   if (kmax_out) *kmax_out = 0;
   if (m == 0) return OR_OK;
   int32_t *sup = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
   if (!sup) return -OR_NOMEM;
-  /* Step 2: support by triangle counting */
   int rc = oracle_support_fwd(n, m, src, dst, sup, NULL);
   if (rc) { free(sup); return rc; }
   adj_t g;
   rc = adj_build(n, m, src, dst, &g);
   if (rc) { free(sup); return rc; }
-
-  /* Step 3: bin sort by support.  order[] is the sorted edge array, pos[e]
-   * the position of e in it, bin[s] the first position holding support s. */
-  int32_t maxsup = 0;
-  for (int64_t i = 0; i < m; ++i) if (sup[i] > maxsup) maxsup = sup[i];
-  int64_t *bin = (int64_t *)calloc((size_t)maxsup + 2, sizeof(int64_t));
-  int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
-  int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+  bins_t b;
+  rc = bins_build(m, sup, &b);
   unsigned char *removed = (unsigned char *)calloc((size_t)m, 1);
-  if (!bin || !order || !pos || !removed) {
-    free(bin); free(order); free(pos); free(removed); free(sup); adj_free(&g);
+  if (rc || !removed) {
+    if (!rc) bins_free(&b);
+    free(removed); free(sup); adj_free(&g);
     return -OR_NOMEM;
   }
-  for (int64_t i = 0; i < m; ++i) bin[sup[i] + 1]++;
-  for (int32_t s = 0; s <= maxsup; ++s) bin[s + 1] += bin[s];
-  {
-    int64_t *next = (int64_t *)malloc(sizeof(int64_t) * ((size_t)maxsup + 1));
-    if (!next) {
-      free(bin); free(order); free(pos); free(removed); free(sup); adj_free(&g);
-      return -OR_NOMEM;
-    }
-    for (int32_t s = 0; s <= maxsup; ++s) next[s] = bin[s];
-    for (int64_t i = 0; i < m; ++i) { pos[i] = next[sup[i]]++; order[pos[i]] = i; }
-    free(next);
-  }
-
-  /* Steps 4-15 */
   int32_t k = 2;
-  int64_t p = 0;
-  while (p < m) {
-    int64_t e = order[p];
-    if (sup[e] > k - 2) { ++k; continue; }          /* Steps 13-15 */
-    int32_t u = src[e], v = dst[e];
-    if (!before(&g, u, v)) { int32_t t = u; u = v; v = t; }  /* Step 6 */
-    for (int64_t j = g.off[u]; j < g.off[u + 1]; ++j) {     /* Step 7 */
-      int32_t w = g.nbr[j];
-      int64_t euw = g.eid[j];
-      if (w == v || removed[euw]) continue;
-      int64_t q = find_nbr(&g, v, w);                       /* Step 8 */
-      if (q < 0) continue;
-      int64_t evw = g.eid[q];
-      if (removed[evw]) continue;
-      int64_t f2[2] = {euw, evw};
-      for (int t = 0; t < 2; ++t) {                         /* Steps 9-10 */
-        int64_t f = f2[t];
-        if (sup[f] > k - 2) {
-          int32_t s = sup[f];
-          int64_t pf = pos[f], pb = bin[s];
-          int64_t g2 = order[pb];
-          order[pb] = f; pos[f] = pb;
-          order[pf] = g2; pos[g2] = pf;
-          bin[s]++;
-          sup[f] = s - 1;
-        }
-      }
-    }
-    phi[e] = k;                                             /* Step 11 */
-    removed[e] = 1;                                         /* Step 12 */
+  for (int64_t p = 0; p < m;) {
+    const int64_t e = b.order[p];
+    if (b.sup[e] > k - 2) { ++k; continue; }
+    remove_edge(&g, &b, removed, src, dst, e, k);
+    phi[e] = k;
     ++p;
   }
   if (kmax_out) *kmax_out = k;
-  free(bin); free(order); free(pos); free(removed); free(sup);
+  bins_free(&b); free(removed); free(sup);
   adj_free(&g);
   return OR_OK;
 }
@@ -575,8 +600,7 @@ int oracle_cohesion(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
 /* Readings (the paper leaves the partition open and is at odds with itself
  * on the 2-class; the design notes list these):
  *   - Memory budget: cap = the most edges a neighbourhood subgraph may hold.
- *   - Partition of a vertex set (Step 3 of Algorithm 3, Step 4 of Procedure
- *     9): parts grown breadth-first over the edges of the graph being
+ *   - Partition of a vertex set (Algorithm 3 and Procedure 9): parts grown breadth-first over the edges of the graph being
  *     partitioned (the current G; H' in Procedure 9), each vertex weighted
  *     by its degree in the graph the neighbourhood subgraphs are taken from
  *     (the current G; the current H), a part's weight sum at most cap
@@ -591,7 +615,7 @@ int oracle_cohesion(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
  *     edges of support 0 as Phi_2; internal edges of later passes go to G_new
  *     with their bound, and Algorithm 4 then starts from k = 2 instead of 3.
  *     Example 3 likewise stops stage 1 after one pass.
- *   - The bound starts at 2 (Example 3; Step 1 says 0): every edge lies in
+ *   - The bound starts at 2 (Example 3; Algorithm 3 starts it at 0): every edge lies in
  *     some neighbourhood subgraph, where its local truss number is >= 2, so
  *     the two starts give the same bounds.
  *   - Algorithm 4 skips a k for which no edge of G_new has bound <= k: U_k
@@ -604,7 +628,7 @@ int oracle_cohesion(int32_t n, int64_t m, const int32_t *src, const int32_t *dst
  *     degree in H.  A scan without new Phi_k edges ends the procedure. */
 enum { OR_CAP = 10, OR_STALL = 11 };
 
-/* Parts grown breadth-first (Step 3 of Algorithm 3, Step 4 of Procedure 9).
+/* Parts grown breadth-first (the partitions of Algorithm 3 and Procedure 9).
  * Vertices qualify when they have an edge with mask[e] set.  A part starts
  * at the smallest-id qualifying vertex not yet placed and grows
  * breadth-first: from each vertex it holds (in the order added) it takes
@@ -677,16 +701,18 @@ int oracle_lower_bounding(int32_t n, int64_t m, const int32_t *src, const int32_
   int rc = OR_OK;
   if (!alive || !active || !deg || !part || !order || !ids || !phi_h || !sup_h) { rc = -OR_NOMEM; goto out; }
   if ((rc = adj_build(n, m, src, dst, &g))) goto out;
-  for (int64_t e = 0; e < m; ++e) { alive[e] = 1; lb[e] = 2; phi2[e] = 0; }  /* Step 1 */
+  for (int64_t e = 0; e < m; ++e) { alive[e] = 1; lb[e] = 2; phi2[e] = 0; }
   int64_t left = m;
-  while (left > 0) {                                                          /* Step 2 */
+  /* passes over the shrinking graph: partition, decompose each part's
+   * neighbourhood subgraph, raise the bounds, drop the internal edges */
+  while (left > 0) {
     const int first = st[0] == 0;
     st[0]++;
     for (int32_t v = 0; v < n; ++v) deg[v] = 0;
     for (int64_t e = 0; e < m; ++e)
       if (alive[e]) { deg[src[e]]++; deg[dst[e]]++; }
     for (int32_t v = 0; v < n; ++v) active[v] = deg[v] > 0;
-    int64_t parts;                                                            /* Step 3 */
+    int64_t parts;
     if (first && first_part) {
       parts = 0;
       for (int32_t v = 0; v < n; ++v) {
@@ -699,22 +725,24 @@ int oracle_lower_bounding(int32_t n, int64_t m, const int32_t *src, const int32_
       if (parts < 0) { rc = (int)parts; goto out; }
     }
     int64_t removed = 0;
-    for (int64_t p = 0; p < parts; ++p) {                                     /* Step 4 */
-      int64_t h = 0;                                                          /* Step 5: NS(P_p) */
+    for (int64_t p = 0; p < parts; ++p) {
+      int64_t h = 0;  /* NS(P_p): live edges with an end in part p */
       for (int64_t e = 0; e < m; ++e)
         if (alive[e] && (part[src[e]] == p || part[dst[e]] == p)) ids[h++] = e;
       if (h == 0) continue;
       if (h > cap) { rc = -OR_CAP; goto out; }
       st[1]++;
       if (h > st[4]) st[4] = h;
-      rc = local_truss(n, src, dst, ids, h, phi_h, sup_h);                    /* Step 6 */
+      rc = local_truss(n, src, dst, ids, h, phi_h, sup_h);
       if (rc) goto out;
       for (int64_t i = 0; i < h; ++i) {
         const int64_t e = ids[i];
-        if (phi_h[i] > lb[e]) lb[e] = phi_h[i];                               /* Step 7 */
-        if (part[src[e]] == p && part[dst[e]] == p) {                         /* internal */
-          if (first && sup_h[i] == 0) { phi2[e] = 1; st[2]++; }               /* Steps 8-9 */
-          else st[3]++;                                                       /* Step 10 */
+        if (phi_h[i] > lb[e]) lb[e] = phi_h[i];  /* Lemma 1: a local truss number is a lower bound */
+        if (part[src[e]] == p && part[dst[e]] == p) {
+          /* an internal edge leaves the graph: to Phi_2 if it closes no
+           * triangle (first pass only), else to G_new with its bound */
+          if (first && sup_h[i] == 0) { phi2[e] = 1; st[2]++; }
+          else st[3]++;
           alive[e] = 0;
           ++removed;
         }
@@ -730,8 +758,8 @@ out:
   return rc;
 }
 
-/* Peel the eligible edges of the subgraph ids[0..h) at level k (Steps 1-5 of
- * Procedure 5, Steps 7-11 of Procedure 9): while an eligible edge has support
+/* Peel the eligible edges of the subgraph ids[0..h) at level k (Procedure 5;
+ * the inner peel of Procedure 9): while an eligible edge has support
  * <= k-2, it joins Phi_k and the two other edges of each of its triangles in
  * the subgraph lose one.  Removed edges get phi = k and gone = 1.  Returns the
  * number of edges output, or a negative error. */
@@ -748,29 +776,29 @@ static int64_t peel_level(int32_t n, const int32_t *src, const int32_t *dst, con
   int64_t count = 0;
   if (!s || !d || !sup || !out || !inq || !queue) { count = -OR_NOMEM; goto done; }
   for (int64_t i = 0; i < h; ++i) { s[i] = src[ids[i]]; d[i] = dst[ids[i]]; }
-  int rc = oracle_support_fwd(n, h, s, d, sup, NULL);                         /* Step 1 */
+  int rc = oracle_support_fwd(n, h, s, d, sup, NULL);
   if (!rc) rc = adj_build(n, h, s, d, &g);
   if (rc) { count = rc; goto done; }
   int64_t qh = 0, qt = 0;
   for (int64_t i = 0; i < h; ++i)
     if (elig[i] && sup[i] <= k - 2) { queue[qt++] = i; inq[i] = 1; }
-  while (qh < qt) {                                                           /* Step 2 */
+  while (qh < qt) {
     const int64_t e = queue[qh++];
     const int32_t u = s[e], v = d[e];
-    for (int64_t j = g.off[u]; j < g.off[u + 1]; ++j) {                       /* Step 4 */
+    for (int64_t j = g.off[u]; j < g.off[u + 1]; ++j) {
       const int32_t w = g.nbr[j];
       const int64_t euw = g.eid[j];
       if (w == v || out[euw]) continue;
       const int64_t q = find_nbr(&g, v, w);
       if (q < 0 || out[g.eid[q]]) continue;
       const int64_t f2[2] = {euw, g.eid[q]};
-      for (int t = 0; t < 2; ++t) {                                           /* Step 5 */
+      for (int t = 0; t < 2; ++t) {
         const int64_t f = f2[t];
         sup[f] -= 1;
         if (elig[f] && !inq[f] && sup[f] <= k - 2) { queue[qt++] = f; inq[f] = 1; }
       }
     }
-    out[e] = 1;                                                               /* Steps 3 and 6 */
+    out[e] = 1;
     phi[ids[e]] = k;
     gone[ids[e]] = 1;
     ++count;
@@ -804,10 +832,13 @@ static int64_t proc9(const adj_t *g, const int32_t *src, const int32_t *dst, con
     goto done;
   }
   for (int64_t i = 0; i < h; ++i) inh[i] = 1;
-  for (;;) {                                                                  /* Steps 2-14 */
+  /* scans of H until one adds nothing to Phi_k; each scan partitions H'
+   * (the edges of H not yet internal to a part of this scan) and peels the
+   * eligible edges of every part's neighbourhood subgraph in H */
+  for (;;) {
     int64_t found = 0;
-    for (int64_t i = 0; i < h; ++i) cov[i] = !inh[i];                         /* Step 2: H' = H */
-    for (;;) {                                                                /* Step 3 */
+    for (int64_t i = 0; i < h; ++i) cov[i] = !inh[i];
+    for (;;) {
       int64_t left = 0;
       for (int32_t v = 0; v < n; ++v) deg[v] = 0;
       for (int64_t i = 0; i < h; ++i) {
@@ -818,11 +849,11 @@ static int64_t proc9(const adj_t *g, const int32_t *src, const int32_t *dst, con
       }
       if (left == 0) break;
       (*scans_out)++;
-      const int64_t parts = grow_partition(g, mask, deg, cap, part, order);  /* Step 4 */
+      const int64_t parts = grow_partition(g, mask, deg, cap, part, order);
       if (parts < 0) { total = parts; goto done; }
       int64_t covered = 0;
-      for (int64_t p = 0; p < parts; ++p) {                                   /* Step 5 */
-        int64_t f = 0;                                                        /* Step 6: F = NS(P_p) in H */
+      for (int64_t p = 0; p < parts; ++p) {
+        int64_t f = 0;  /* F = NS(P_p) in H */
         for (int64_t i = 0; i < h; ++i) {
           if (!inh[i]) continue;
           const int32_t a = part[src[ids[i]]], b = part[dst[ids[i]]];
@@ -830,20 +861,20 @@ static int64_t proc9(const adj_t *g, const int32_t *src, const int32_t *dst, con
         }
         if (f == 0) continue;
         if (f > cap) { total = -OR_CAP; goto done; }
-        const int64_t c = peel_level(n, src, dst, fid, f, elig, k, phi, gone);  /* Steps 7-12 */
+        const int64_t c = peel_level(n, src, dst, fid, f, elig, k, phi, gone);
         if (c < 0) { total = c; goto done; }
         found += c;
         for (int64_t j = 0; j < f; ++j) {
           const int64_t i = fpos[j];
           if (gone[ids[i]]) inh[i] = 0;
           const int32_t a = part[src[ids[i]]], b = part[dst[ids[i]]];
-          if (a == p && b == p && !cov[i]) { cov[i] = 1; ++covered; }         /* Step 13 */
+          if (a == p && b == p && !cov[i]) { cov[i] = 1; ++covered; }
         }
       }
       if (covered == 0) { total = -OR_STALL; goto done; }
     }
     total += found;
-    if (found == 0) break;                                                    /* Step 14 */
+    if (found == 0) break;
   }
 done:
   free(mask); free(order);
@@ -873,16 +904,18 @@ int oracle_bottom_up(int32_t n, int64_t m, const int32_t *src, const int32_t *ds
     phi[e] = phi2[e] ? 2 : 0;
     left += !phi2[e];
   }
-  int32_t k = kstart;                                                         /* Step 2 */
-  while (left > 0) {                                                          /* Step 7 */
+  /* one level k at a time: U_k = the ends of the G_new edges with bound <= k,
+   * Phi_k from the candidate subgraph NS(U_k) */
+  int32_t k = kstart;
+  while (left > 0) {
     int32_t lmin = 0x7fffffff;
     for (int64_t e = 0; e < m; ++e)
       if (!gone[e] && lb[e] < lmin) lmin = lb[e];
     if (lmin > k) k = lmin;
-    for (int32_t v = 0; v < n; ++v) inu[v] = 0;                               /* Step 3: U_k */
+    for (int32_t v = 0; v < n; ++v) inu[v] = 0;
     for (int64_t e = 0; e < m; ++e)
       if (!gone[e] && lb[e] <= k) { inu[src[e]] = 1; inu[dst[e]] = 1; }
-    int64_t h = 0;                                                            /* Steps 4-5: NS(U_k) */
+    int64_t h = 0;  /* NS(U_k) */
     for (int64_t e = 0; e < m; ++e)
       if (!gone[e] && (inu[src[e]] || inu[dst[e]])) {
         internal[h] = inu[src[e]] && inu[dst[e]];
@@ -892,7 +925,7 @@ int oracle_bottom_up(int32_t n, int64_t m, const int32_t *src, const int32_t *ds
     if (h > st[3]) st[3] = h;
     int64_t c;
     if (h <= cap) {
-      c = peel_level(n, src, dst, ids, h, internal, k, phi, gone);            /* Step 6: Procedure 5 */
+      c = peel_level(n, src, dst, ids, h, internal, k, phi, gone);  /* Procedure 5 */
     } else {
       st[1]++;
       c = proc9(&g, src, dst, ids, h, internal, k, cap, phi, gone, &st[2]);
@@ -900,7 +933,7 @@ int oracle_bottom_up(int32_t n, int64_t m, const int32_t *src, const int32_t *ds
     if (c < 0) { rc = (int)c; goto out; }
     left -= c;
     st[4] = k;
-    k += 1;                                                                   /* Step 8 */
+    k += 1;
   }
   if (info) for (int i = 0; i < 5; ++i) info[i] = st[i];
 out:

@@ -129,7 +129,7 @@ def random_graph(rng, n, p):
 
 def x_brute(n, edges, sup, i, w):
     """Largest x such that at least x edges incident to w, other than edge i,
-    have support >= x (Procedure 6, Step 5)."""
+    have support >= x (Procedure 6)."""
     others = [sup[j] for j, (a, b) in enumerate(edges) if j != i and (a == w or b == w)]
     best = 0
     for x in range(len(others) + 1):
@@ -139,7 +139,7 @@ def x_brute(n, edges, sup, i, w):
 
 
 def psi_brute(n, edges, sup):
-    """psi(e) = min{sup(e), x_u, x_v} + 2 for every edge (Procedure 6, Step 6)."""
+    """psi(e) = min{sup(e), x_u, x_v} + 2 for every edge (Procedure 6)."""
     return np.array([min(sup[i], x_brute(n, edges, sup, i, u), x_brute(n, edges, sup, i, v)) + 2
                      for i, (u, v) in enumerate(edges)], dtype=np.int64)
 
