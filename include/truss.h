@@ -91,7 +91,7 @@ typedef struct truss_graph {
 #define TRUSS_PEEL_SPARSE 1 /* worklist: enqueue an edge when its support drops to k-2 */
 #define TRUSS_PEEL_DENSE 2  /* re-scan every live edge after each sub-round      */
 
-/* Membership test "(v, w) in E_G" while peeling (Algorithm 2, Step 8). */
+/* Membership test (is (v, w) an edge of E_G?) while peeling (Algorithm 2). */
 #define TRUSS_PROBE_AUTO 0    /* hash table                                      */
 #define TRUSS_PROBE_HASH 1    /* hash table over the edges, as Section 3.2 keeps E_G */
 #define TRUSS_PROBE_BSEARCH 2 /* binary search of the other endpoint's sorted row  */
@@ -240,10 +240,10 @@ int truss_topdown(const truss_graph *g, int32_t t, int32_t *truss_out, int32_t *
 
 /* ---- Algorithm 1 (Section 3.1) as a comparator ------------------------------- */
 /* The decomposition of Algorithm 1 (Cohen): sup(e) = |nb(u) ∩ nb(v)| by
- * merging the two full sorted rows (Steps 2-3); then for k = 3, 4, ... the
+ * merging the two full sorted rows; then for k = 3, 4, ... the
  * edges with sup < k-2 leave, each finding its triangles by merging the two
- * full rows again (Step 5; removed edges are only marked) and decrementing the
- * two other edges of each (Steps 6-7).  truss_out (device) int32[m] as in
+ * full rows again (removed edges are only marked) and decrementing the
+ * two other edges of each.  truss_out (device) int32[m] as in
  * "Output indexing" — the same truss numbers as truss_decompose.  stats
  * (host, nullable): support_work and peel_work = row entries merged (for
  * each edge deg(u) + deg(v) once in each stage, i.e. the sum over vertices of
@@ -303,14 +303,14 @@ int truss_cohesion(const truss_graph *g, const truss_options *opts, truss_cohesi
  * pass of Algorithm 3 sees the input graph, so only it outputs internal edges
  * of support 0 as Phi_2; Algorithm 4 starts at k = 2 after a second pass. */
 typedef struct truss_bottomup_stats {
-  int64_t passes;        /* LowerBounding passes (Algorithm 3, Step 2)                */
+  int64_t passes;        /* LowerBounding passes (Algorithm 3)                        */
   int64_t subgraphs;     /* neighbourhood subgraphs decomposed by LowerBounding       */
   int64_t phi2_edges;    /* |Phi_2| output by LowerBounding                           */
   int64_t gnew_edges;    /* |G_new|                                                   */
   int64_t max_subgraph;  /* most edges in one neighbourhood subgraph of LowerBounding  */
-  int64_t candidates;    /* candidate subgraphs NS(U_k) (Algorithm 4, Steps 3-5)      */
+  int64_t candidates;    /* candidate subgraphs NS(U_k) (Algorithm 4)                 */
   int64_t proc9_calls;   /* candidates above cap (Procedure 9)                        */
-  int64_t proc9_scans;   /* partitions of H' made by Procedure 9 (its Step 4)         */
+  int64_t proc9_scans;   /* partitions of H' made by Procedure 9                      */
   int64_t max_candidate; /* most edges in a candidate subgraph                        */
   int64_t device_calls;  /* subgraphs run on the device                               */
   int64_t bytes_h2d, bytes_d2h;

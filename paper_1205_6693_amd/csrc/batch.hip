@@ -7,7 +7,7 @@
 // the workgroup's scratch slot, rows sorted by neighbour id (a rank sort that
 // also finds duplicate edges), the support of every edge by intersecting the
 // shorter endpoint row with the longer one (Definition 1), and
-// level-synchronous peeling as in Algorithm 2, Steps 4-15, with the same
+// level-synchronous peeling of Algorithm 2, with the same
 // snapshot frontier, smallest-id ownership and exactly-once decrements as the
 // device-wide path.  Edge ids are the graph's input positions, so truss
 // numbers land directly in the caller's packed output.
@@ -437,7 +437,7 @@ __device__ void process_graph(const BatchArgs& A, const Slot& S, int g, Lds<T>& 
   }
   __syncthreads();
   const unsigned long long t2 = wall_clock64();
-  // 5. peeling, level by level (Algorithm 2, Steps 4-15, level-synchronous)
+  // 5. peeling, level by level (Algorithm 2, level-synchronous)
   int32_t* alist[2] = {S.colA, S.colA + A.max_m};
   int32_t* fq[2] = {S.eidA, S.eidA + A.max_m};
   int acnt = m, acur = 0, csr_live = m;

@@ -8,7 +8,7 @@
 // the device and decomposed there by the in-memory path.  The budget is the
 // most edges a subgraph sent to the device may hold.
 //
-// Partition of a vertex set (Step 3 of Algorithm 3, Step 4 of Procedure 9):
+// Partition of a vertex set (Algorithm 3 and Procedure 9):
 // parts are grown breadth-first over the edges of the graph being partitioned
 // (the current G; H' in Procedure 9).  A part starts at the smallest-id
 // unplaced vertex that has such an edge and takes, from each vertex it holds
@@ -399,15 +399,15 @@ int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, 
   std::vector<uint8_t> alive((size_t)g.m, 1);
   std::vector<int64_t> deg((size_t)g.n);
   for (int32_t v = 0; v < g.n; ++v) deg[v] = g.end[v] - g.off[v];
-  lb.assign((size_t)g.m, 2);  // Step 1 (the bound starts at 2, as in Example 3)
+  lb.assign((size_t)g.m, 2);  // the bound starts at 2, as in Example 3
   phi2.assign((size_t)g.m, 0);
   Parts P;
   Staged S;
   int64_t left = g.m;
-  while (left > 0) {  // Step 2
+  while (left > 0) {  // one pass over the remaining graph
     const bool first = R.st.passes == 0;
     R.st.passes += 1;
-    if (first && first_part) {  // Step 3: the caller's partition
+    if (first && first_part) {  // the caller's partition
       int32_t parts = 0;
       P.part.assign((size_t)g.n, -1);
       for (int32_t v = 0; v < g.n; ++v) {
@@ -427,12 +427,12 @@ int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, 
       P.order.assign((size_t)cnt[(size_t)parts], 0);
       for (int32_t v = 0; v < g.n; ++v)
         if (P.part[v] >= 0) P.order[(size_t)cnt[P.part[v]]++] = v;
-    } else if (!grow_parts(rows_of(g), alive.data(), deg.data(), R.cap, P)) {  // Step 3
+    } else if (!grow_parts(rows_of(g), alive.data(), deg.data(), R.cap, P)) {
       return TRUSS_E_WORKSPACE;
     }
     int64_t removed = 0;
-    for (int64_t p = 0; p < P.count(); ++p) {  // Step 4
-      // Step 5: H = NS(P_p) in the current G; flag = internal
+    for (int64_t p = 0; p < P.count(); ++p) {
+      // H = NS(P_p) in the current G; flag = internal
       S.ids.clear();
       S.flag.clear();
       for (int64_t i = P.start[(size_t)p]; i < P.start[(size_t)p + 1]; ++i) {
@@ -455,16 +455,16 @@ int lower_bounding(Run& R, const int32_t* first_part, std::vector<int32_t>& lb, 
       }
       R.st.subgraphs += 1;
       R.st.max_subgraph = std::max(R.st.max_subgraph, h);
-      int rc = run_staged(g, R.D, S, false, 2, 0, true, R.opts, R.s);  // Step 6
+      int rc = run_staged(g, R.D, S, false, 2, 0, true, R.opts, R.s);  // local truss numbers
       if (rc) return rc;
       for (int64_t i = 0; i < h; ++i) {
         const int32_t e = S.ids[(size_t)i];
-        lb[(size_t)e] = std::max(lb[(size_t)e], R.D.h_out[i]);  // Step 7
+        lb[(size_t)e] = std::max(lb[(size_t)e], R.D.h_out[i]);  // Lemma 1
         if (!S.flag[(size_t)i]) continue;
-        if (first && R.D.h_sup[i] == 0) {  // Steps 8-9
+        if (first && R.D.h_sup[i] == 0) {  // Phi_2
           phi2[(size_t)e] = 1;
           R.st.phi2_edges += 1;
-        } else {  // Step 10
+        } else {  // G_new
           R.st.gnew_edges += 1;
         }
         alive[(size_t)e] = 0;
@@ -617,10 +617,10 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& li
   Parts P;
   Staged F;
   R.st.proc9_calls += 1;
-  for (;;) {  // Steps 2-14
+  for (;;) {  // scans of H until one adds nothing to Phi_k
     int64_t found = 0;
-    for (size_t i = 0; i < h; ++i) cov[i] = !inh[i];  // Step 2: H' = H
-    for (;;) {                                        // Step 3
+    for (size_t i = 0; i < h; ++i) cov[i] = !inh[i];  // H' = H
+    for (;;) {
       std::fill(deg.begin(), deg.end(), 0);
       PieceSums lc;
       parallel_pieces((int64_t)h, kGrain, [&](int64_t lo, int64_t hi, int t) {
@@ -656,10 +656,10 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& li
         }
       });
       const Rows hrows{rows.n, moff.data(), moff.data() + 1, mnbr.data(), meid.data()};
-      if (!grow_parts(hrows, mask.data(), deg.data(), R.cap, P)) return TRUSS_E_WORKSPACE;  // Step 4
+      if (!grow_parts(hrows, mask.data(), deg.data(), R.cap, P)) return TRUSS_E_WORKSPACE;
       int64_t covered = 0;
-      for (int64_t p = 0; p < P.count(); ++p) {  // Step 5
-        // Step 6: F = NS(P_p) in the current H; flag = eligible (internal to F and to H)
+      for (int64_t p = 0; p < P.count(); ++p) {
+        // F = NS(P_p) in the current H; flag = eligible (internal to F and to H)
         // local edge indices of F, gathered piecewise over the part's vertices
         const int64_t p0 = P.start[(size_t)p], np = P.start[(size_t)p + 1] - p0;
         for (auto& x : piece) x.clear();
@@ -691,19 +691,19 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& li
             F.flag[(size_t)j] = inside && H.flag[i] ? 1 : 0;
           }
         });
-        const int rc = run_staged(g, R.D, F, true, k, k, false, R.opts, R.s);  // Steps 7-11
+        const int rc = run_staged(g, R.D, F, true, k, k, false, R.opts, R.s);  // peel level k of F
         if (rc) return rc;
         PieceSums fc, cc;
         parallel_pieces(nf, kGrain, [&](int64_t lo, int64_t hi, int t) {
           for (int64_t j = lo; j < hi; ++j) {
             const int32_t x = fidx[(size_t)j];
             const size_t i = (size_t)(x >= 0 ? x : ~x);
-            if (F.flag[(size_t)j] && R.D.h_out[j] == k) {  // Step 12
+            if (F.flag[(size_t)j] && R.D.h_out[j] == k) {  // joins Phi_k
               B.output_shared(F.ids[(size_t)j], k);
               inh[i] = 0;
               fc.v[t] += 1;
             }
-            if (x >= 0 && !cov[i]) {  // Step 13 (each internal edge of F appears once)
+            if (x >= 0 && !cov[i]) {  // leaves H' (each internal edge of F appears once)
               cov[i] = 1;
               cc.v[t] += 1;
             }
@@ -719,7 +719,7 @@ int procedure9(BottomUp& B, const Staged& H, int32_t k, std::vector<int32_t>& li
       }
     }
     *found_total += found;
-    if (found == 0) break;  // Step 14
+    if (found == 0) break;
   }
   return TRUSS_OK;
 }
@@ -754,9 +754,9 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
   std::vector<uint8_t> inlist((size_t)g.n, 0);
   size_t ap = 0;
   Staged H;
-  int32_t k = R.st.kstart;  // Step 2
-  while (B.left > 0) {      // Step 7
-    // Step 3: U_k = ends of the remaining edges with bound <= k
+  int32_t k = R.st.kstart;
+  while (B.left > 0) {  // one level k at a time
+    // U_k = ends of the remaining edges with bound <= k
     for (;;) {
       while (ap < sorted.size() && lb[(size_t)sorted[ap]] <= k) {
         const int32_t e = sorted[ap++];
@@ -771,7 +771,7 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
       if (B.active_left > 0) break;
       k = lb[(size_t)sorted[ap]];  // no candidate at this k: Phi_k is empty
     }
-    // Steps 4-5: H = NS(U_k); flag = internal
+    // H = NS(U_k); flag = internal
     size_t keep = 0;
     for (size_t i = 0; i < ulist.size(); ++i) {
       const int32_t u = ulist[i];
@@ -803,7 +803,7 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
     R.st.candidates += 1;
     R.st.max_candidate = std::max(R.st.max_candidate, (int64_t)H.ids.size());
     int64_t found = 0;
-    const int rc = (int64_t)H.ids.size() <= R.cap ? procedure5(B, H, k, &found)  // Step 6
+    const int rc = (int64_t)H.ids.size() <= R.cap ? procedure5(B, H, k, &found)
                                                    : procedure9(B, H, k, lid, &found);
     if (rc) return rc;
     if (found > 0) R.st.kmax = k;
@@ -812,7 +812,7 @@ int bottom_up(Run& R, const std::vector<int32_t>& lb, const std::vector<uint8_t>
               k, H.ids.size(), (int64_t)H.ids.size() <= R.cap ? 5 : 9, (long long)found, (long long)B.left,
               ms_since(t0));
     g.compact(B.gone.data(), 0, B.left);
-    k += 1;  // Step 8
+    k += 1;
   }
   return TRUSS_OK;
 }

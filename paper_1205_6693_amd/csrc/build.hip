@@ -1,7 +1,7 @@
 // Graph build: validation of the simple-graph contract (Section 2), canonical
 // edge ids, the symmetric CSR with edge ids, and the (degree, id) orientation
 // used for triangle listing (the in-memory triangle counting that Algorithm 2,
-// Step 2 relies on; the smaller-degree rule of Step 6 and Theorem 1).
+// starts from; the smaller-degree rule of its triangle walk and Theorem 1).
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -204,7 +204,7 @@ __global__ void k_ocsr(const int32_t* __restrict__ col, const int32_t* __restric
   }
 }
 
-// ---- edge hash table (Algorithm 2, Step 8) -------------------------------------------------
+// ---- edge hash table (the membership test of Algorithm 2) ---------------------------------
 
 __global__ void k_etab_clear(EdgeSlot* __restrict__ tab, int64_t size) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < size; i += (int64_t)gridDim.x * blockDim.x) {

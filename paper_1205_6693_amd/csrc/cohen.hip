@@ -1,8 +1,8 @@
 // Algorithm 1 (Cohen's truss decomposition, Section 3.1) on the device, as a
 // comparator for the in-memory path of Algorithm 2.
 //
-// Support (Steps 2-3): sup(e) = |nb(u) ∩ nb(v)| by merging the two full sorted
-// rows.  Peeling (Steps 4-12): for k = 3, 4, ... every edge with sup < k-2
+// Support: sup(e) = |nb(u) ∩ nb(v)| by merging the two full sorted
+// rows.  Peeling: for k = 3, 4, ... every edge with sup < k-2
 // leaves (its truss number is k-1); W = nb(u) ∩ nb(v) is again a merge of the
 // two full rows, reading removed edges as deleted (the implicit deletion of
 // Section 3.1: rows are never compacted), and the two other edges of each
@@ -109,7 +109,7 @@ __global__ void k_cohen_reset(CohenCtl* c, int full) {
   }
 }
 
-// Level start (Step 4 at a new k): live edges with sup < k-2 form the frontier
+// Level start (a new k): live edges with sup < k-2 form the frontier
 // of round r; also counts the live edges left and their smallest support.
 __global__ void __launch_bounds__(kT) k_cohen_start(int2* __restrict__ sr, int64_t m, int k, int r,
                                                     int32_t* __restrict__ q, int32_t* __restrict__ truss,
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kT) k_cohen_start(int2* __restrict__ sr, int64
 }
 
 // One round: every frontier edge (stamp r) finds W by merging the full rows
-// and breaks the triangles it owns (Steps 5-8).
+// and breaks the triangles it owns.
 __global__ void __launch_bounds__(kT) k_cohen_round(const int64_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ col, const int32_t* __restrict__ seid,
                                                     const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
@@ -244,7 +244,7 @@ int cohen_decompose(const DevGraph& dg, int2* sr, int32_t* truss, Arena& a, Cohe
       r += 1;
     }
     r += 1;
-    k += 1;  // the live edges now form the k-truss (Step 9)
+    k += 1;  // the live edges now form the k-truss
   }
   TRUSS_HIP(hipEventRecord(ev[2], s));
   TRUSS_HIP(hipEventSynchronize(ev[2]));

@@ -108,7 +108,7 @@ __device__ __forceinline__ IdxT lower_bound_i32(const int* __restrict__ a, IdxT 
 }
 
 // ---- edge hash table ------------------------------------------------------------
-// The membership test of Algorithm 2, Step 8 ("(v, w) in E_G") through a
+// The membership test of Algorithm 2 (is (v, w) an edge of E_G?) through a
 // hashtable over E_G (Section 3.2): open addressing with linear probing, key
 // (min << 32 | max), value the canonical edge id.  At most half full.
 struct EdgeSlot {

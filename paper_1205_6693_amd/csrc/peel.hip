@@ -1,4 +1,4 @@
-// Peeling (Algorithm 2, Steps 4-15, made level-synchronous).
+// Peeling (Algorithm 2, made level-synchronous).
 //
 // Level k removes every live edge whose support is at most k-2 and gives it
 // truss number k.  Within a level the frontier F_r of sub-round r is a snapshot:
@@ -7,13 +7,13 @@
 // whose three edges are not removed and which has at least one edge in F_r is
 // destroyed in round r; only its F_r edge of smallest id processes it, and that
 // edge decrements each of the triangle's other edges that is not in F_r exactly
-// once (the two decrements of Algorithm 2, Step 9).  After round r every live
+// once (the two decrements of Algorithm 2).  After round r every live
 // edge's support therefore equals its support in the graph without
 // F_0 ∪ ... ∪ F_r, which is the sequential invariant, so the truss numbers
 // match Algorithm 2 whatever the order of removals inside a level.
 //
 // Triangles through a frontier edge e = (u, v) are found as in Algorithm 2,
-// Steps 6-8: walk the adjacency row of the endpoint with the shorter live row,
+// by its triangle walk: walk the adjacency row of the endpoint with the shorter live row,
 // and look each neighbour w up in the other endpoint's sorted row by binary
 // search.  Deleted edges are only marked (Section 3.1); the rows are compacted
 // in place whenever the live edge count has halved.
@@ -43,7 +43,7 @@
 // Each level runs in one of four ways, decided when its first frontier is
 // known: the frontier mode (SPARSE enqueues an edge the moment its support
 // drops from k-1 to k-2, the queue of Section 3.1; DENSE re-scans the live
-// edges after every sub-round) and the membership probe of Step 8 (the edge
+// edges after every sub-round) and the membership probe (the edge
 // hash table, or binary search of the other endpoint's row).  The scheduler
 // (plain, a fixed heuristic, or the learned network evaluated by the control
 // wavefront) only picks among these exact methods.
@@ -485,7 +485,7 @@ __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t
   }
 #pragma unroll
   for (int q = 0; q < kNI; ++q) ok[q] = ok[q] && !removed_at(s1[q], r);
-  // the second other edge (b, w), Step 8: hash table or binary search
+  // the second other edge (b, w): hash table or binary search
   if (probe == 0) {
     unsigned long long key[kNI], h[kNI];
     ulonglong2 sl[kNI];

@@ -3,7 +3,7 @@
 // Every triangle {a, b, c} is listed exactly once through the (degree, id)
 // orientation: with a before b before c, it is found from a as b in N+(a) and
 // c in N+(a) ∩ N+(b).  This is the in-memory triangle counting that Algorithm 2,
-// Step 2 relies on, and the orientation bounds |N+(a)| by 2*sqrt(m) as in the
+// starts from, and the orientation bounds |N+(a)| by 2*sqrt(m) as in the
 // proof of Theorem 1, so N+(a) fits in LDS for every vertex of the target
 // graphs.  The three edges of a found triangle get +1: (a,b) and (a,c) in LDS
 // counters private to the workgroup that owns a (flushed once per edge), and
