@@ -321,13 +321,21 @@ __device__ void walk_pairs(const WalkTabs& W, int nrows, int lo, int hi, const i
   if (lane == 0 && acc && kc >= 0) atomicAdd(&W.cnt[W.wi[kc]], acc);
 }
 
-// Stages N+(a) for the hash method: the table, zeroed counts and the walk
-// rows (non-empty N+(b) only, compacted by a scan).  nth threads take part
-// (a wavefront or the whole workgroup; scratch: kT / kWave ints + 2).
-// Returns the number of walk rows; W.pre[nrows] is the number of pairs.
-template <int LOGTAB, int NTH>
+// Stages N+(a) for the hash method: the table, the list nb, zeroed counts and
+// the rows.  A b with |N+(b)| > kRev |N+(a)| is a searched row instead of a
+// walked one: rather than walking its pairs, each c in N+(a) is looked up in
+// the sorted N+(b) (see search_rows).  Walked rows (non-empty, compacted by a
+// scan) fill pre, offj, wi from index 0; searched rows fill them from the top
+// (searched row r: position wi[MAXD-1-r], N+(b) at ocol[offj[MAXD-1-r] ..] of
+// length pre[MAXD-r]); as walked + searched <= |N+(a)| <= MAXD they never
+// meet.  nth threads take part (a wavefront or the whole workgroup; scratch:
+// NTH / kWave entries); *nrev (LDS, zero on entry) receives the searched rows.
+// Returns the number of walked rows; pre[nrows] is the number of their pairs.
+constexpr int kRev = 8;
+template <int LOGTAB, int NTH, int MAXD>
 __device__ int stage_rows(const int64_t* __restrict__ orow, const int32_t* __restrict__ ocol, int64_t base, int d,
-                          int2* tab, int* pre, int* offj, int* wi, int* cnt, unsigned long long* scratch) {
+                          int2* tab, int* nb, int* pre, int* offj, int* wi, int* cnt, int* nrev,
+                          unsigned long long* scratch) {
   const int tid = NTH == kWave ? lane_id() : (int)threadIdx.x;
   constexpr int NW = NTH / kWave;
   const int w = tid / kWave;
@@ -344,7 +352,15 @@ __device__ int stage_rows(const int64_t* __restrict__ orow, const int32_t* __res
       ob = orow[b];
       db = (int)(orow[b + 1] - ob);
       tab_insert<LOGTAB>(tab, b, i);
+      nb[i] = b;
       cnt[i] = 0;
+      if (db > kRev * d) {
+        const int r = atomicAdd(nrev, 1);
+        pre[MAXD - r] = db;
+        offj[MAXD - 1 - r] = (int)ob;
+        wi[MAXD - 1 - r] = i;
+        db = 0;  // not walked
+      }
     }
     const unsigned long long v = db > 0 ? (((unsigned long long)db) << 32) | 1ULL : 0ULL;
     const unsigned long long inc = wave_inclusive_sum(v);
@@ -377,6 +393,30 @@ __device__ int stage_rows(const int64_t* __restrict__ orow, const int32_t* __res
   return nrows;
 }
 
+// One wavefront checks pairs [lo, hi) of the searched rows: pair t is
+// (searched row t / d, c = nb[t % d]); c in N+(b) closes the triangle
+// {a, b, c}, counted on (a, b), (a, c) in LDS and on (b, c) at its oriented
+// position.  Each triangle is still found once: c must be an out-neighbour of
+// b, as in the walk.
+template <int MAXD>
+__device__ void search_rows(const int* nb, const int* pre, const int* offj, const int* wi, int* cnt, int d, int lo,
+                            int hi, const int32_t* __restrict__ ocol, int32_t* __restrict__ supo) {
+  for (int t = lo + lane_id(); t < hi; t += kWave) {
+    const int r = t / d, j = t - r * d;
+    const int i = wi[MAXD - 1 - r];
+    if (j == i) continue;
+    const int32_t c = nb[j];
+    const int64_t off = offj[MAXD - 1 - r];
+    const int64_t end = off + pre[MAXD - r];
+    const int64_t p = lower_bound_i32<int64_t>(ocol, off, end, c);
+    if (p < end && ocol[p] == c) {
+      atomicAdd(&cnt[i], 1);
+      atomicAdd(&cnt[j], 1);
+      atomicAdd(&supo[p], 1);
+    }
+  }
+}
+
 // bin 0, hash: a wavefront per vertex, vertices fetched kFetch0 at a time
 constexpr int kFetch0 = 16;
 __global__ void __launch_bounds__(kT) k_sup_hash_wave(const int64_t* __restrict__ orow,
@@ -386,11 +426,13 @@ __global__ void __launch_bounds__(kT) k_sup_hash_wave(const int64_t* __restrict_
   constexpr int W = kT / kWave;
   constexpr int LOGTAB = 7;
   __shared__ int2 s_tab[W][1 << LOGTAB];
+  __shared__ int s_nb[W][kWaveMax];
   __shared__ int s_pre[W][kWaveMax + 1];
   __shared__ int s_offj[W][kWaveMax];
   __shared__ int s_wi[W][kWaveMax];
   __shared__ int s_cnt[W][kWaveMax];
   __shared__ int s_own[W][kWave];
+  __shared__ int s_nrev[W];
   if (ctl->act[0] != kHash) return;
   const int w = threadIdx.x / kWave, lane = lane_id();
   const int count = atomic_load_relaxed(&ctl->cnt[0]);
@@ -405,9 +447,12 @@ __global__ void __launch_bounds__(kT) k_sup_hash_wave(const int64_t* __restrict_
       const int32_t a = vlist[idx];
       const int64_t base = orow[a];
       const int d = (int)(orow[a + 1] - base);
-      const int nrows = stage_rows<LOGTAB, kWave>(orow, ocol, base, d, s_tab[w], s_pre[w], s_offj[w], s_wi[w],
-                                                  s_cnt[w], nullptr);
+      if (lane == 0) s_nrev[w] = 0;
+      wave_sync();
+      const int nrows = stage_rows<LOGTAB, kWave, kWaveMax>(orow, ocol, base, d, s_tab[w], s_nb[w], s_pre[w],
+                                                            s_offj[w], s_wi[w], s_cnt[w], &s_nrev[w], nullptr);
       walk_pairs<LOGTAB>(T, nrows, 0, s_pre[w][nrows], ocol, supo);
+      search_rows<kWaveMax>(s_nb[w], s_pre[w], s_offj[w], s_wi[w], s_cnt[w], d, 0, s_nrev[w] * d, ocol, supo);
       wave_sync();
       if (lane < d) {
         const int cc = s_cnt[w][lane];
@@ -428,19 +473,23 @@ __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8, 8))
   constexpr int LOGTAB = MAXD == 1024 ? 11 : 13;
   constexpr int NW = NTH / kWave;
   __shared__ int2 s_tab[1 << LOGTAB];
+  __shared__ int s_nb[MAXD];
   __shared__ int s_pre[MAXD + 1];
   __shared__ int s_offj[MAXD];
   __shared__ int s_wi[MAXD];
   __shared__ int s_cnt[MAXD];
   __shared__ int s_own[NW][kWave];
   __shared__ unsigned long long s_scr[NW];
-  __shared__ int s_idx;
+  __shared__ int s_idx, s_nrev;
   if (ctl->act[bin] != kHash) return;
   const int w = threadIdx.x / kWave;
   const int count = atomic_load_relaxed(&ctl->cnt[bin]);
   WalkTabs T{s_pre, s_offj, s_wi, s_tab, s_cnt, s_own[w]};
   for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(&ctl->fetch[bin], 1);
+    if (threadIdx.x == 0) {
+      s_idx = atomicAdd(&ctl->fetch[bin], 1);
+      s_nrev = 0;
+    }
     __syncthreads();
     const int idx = s_idx;
     __syncthreads();
@@ -448,9 +497,13 @@ __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8, 8))
     const int32_t a = vlist[(int64_t)bin * n + idx];
     const int64_t base = orow[a];
     const int d = (int)(orow[a + 1] - base);
-    const int nrows = stage_rows<LOGTAB, NTH>(orow, ocol, base, d, s_tab, s_pre, s_offj, s_wi, s_cnt, s_scr);
+    const int nrows = stage_rows<LOGTAB, NTH, MAXD>(orow, ocol, base, d, s_tab, s_nb, s_pre, s_offj, s_wi, s_cnt,
+                                                    &s_nrev, s_scr);
     const int64_t total = s_pre[nrows];
     walk_pairs<LOGTAB>(T, nrows, (int)(total * w / NW), (int)(total * (w + 1) / NW), ocol, supo);
+    const int64_t stot = (int64_t)s_nrev * d;
+    search_rows<MAXD>(s_nb, s_pre, s_offj, s_wi, s_cnt, d, (int)(stot * w / NW), (int)(stot * (w + 1) / NW), ocol,
+                      supo);
     __syncthreads();
     for (int i = threadIdx.x; i < d; i += NTH) {
       const int cc = s_cnt[i];
