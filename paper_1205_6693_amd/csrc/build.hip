@@ -204,31 +204,52 @@ __global__ void k_ocsr(const int32_t* __restrict__ col, const int32_t* __restric
   }
 }
 
-// ---- edge hash table (the membership test of Algorithm 2) ---------------------------------
+// ---- row hash tables (the membership test of Algorithm 2) -----------------------------------
 
-__global__ void k_etab_clear(EdgeSlot* __restrict__ tab, int64_t size) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < size; i += (int64_t)gridDim.x * blockDim.x) {
-    tab[i].key = kEmptyKey;
-    tab[i].eid = -1;
+// slots of v's table: the power of two >= 2 deg(v) (0 for an isolated vertex)
+__global__ void k_rtab_sizes(const int64_t* __restrict__ row_ptr, int32_t n, int32_t* __restrict__ tsz) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t d = row_ptr[v + 1] - row_ptr[v];
+  int64_t sz = 0;
+  if (d > 0) {
+    sz = 2;
+    while (sz < 2 * d) sz <<= 1;
   }
+  tsz[v] = (int32_t)sz;
 }
 
-__global__ void k_etab_insert(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
-                              EdgeSlot* __restrict__ tab, unsigned long long mask) {
+__global__ void k_rtab_clear(int2* __restrict__ rtab, const int64_t* __restrict__ rtoff, int32_t n, int64_t cap) {
+  const int64_t total = rtoff[n];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total && i < cap;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rtab[i] = make_int2(-1, 0);
+}
+
+// a thread per edge (u, v) inserts v into u's table and u into v's table
+// (consecutive edges share u, so the first inserts of a warp land together)
+__device__ __forceinline__ void rtab_put(int2* __restrict__ rtab, const int64_t* __restrict__ rtoff, int32_t v,
+                                         int32_t w, int32_t e) {
+  const int64_t off = rtoff[v];
+  const int lg = row_table_lg(rtoff[v + 1] - off);
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = row_slot(w, lg);
+  // neighbours are distinct and the table is at most half full: a free slot is found
+  while (atomicCAS(&rtab[off + h].x, -1, w) != -1) h = (h + 1) & mask;
+  rtab[off + h].y = e;
+}
+
+__global__ void k_rtab_insert(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
+                              const int64_t* __restrict__ rtoff, int2* __restrict__ rtab) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= m) return;
-  const unsigned long long key = edge_key(eu[e], ev[e]);
-  unsigned long long h = mix64(key) & mask;
-  // keys are distinct and the table is at most half full, so a free slot is found
-  while (atomicCAS(&tab[h].key, kEmptyKey, key) != kEmptyKey) h = (h + 1) & mask;
-  tab[h].eid = (int)e;
+  const int32_t u = eu[e], v = ev[e];
+  rtab_put(rtab, rtoff, u, v, (int32_t)e);
+  rtab_put(rtab, rtoff, v, u, (int32_t)e);
 }
 
-int64_t etab_size(int64_t m) {
-  int64_t size = 1024;
-  while (size < 2 * m) size <<= 1;
-  return size;
-}
+// capacity bound: 2^ceil(log2(2d)) < 4d for d >= 1, so all tables fit in 8m slots
+inline int64_t rtab_capacity(int64_t m) { return 8 * m + 2; }
 
 int read_err(const int* d_err, hipStream_t s) {
   int h = kNoErr;
@@ -261,8 +282,9 @@ struct Layout {
   int64_t *opos;
   int32_t *rtmp;
   int64_t *stmp;
-  EdgeSlot* etab;
-  int64_t etab_n;
+  int2* rtab;
+  int64_t* rtoff;
+  int32_t* tsz;
 };
 
 void carve(const truss_graph* g, Arena& a, Layout& L) {
@@ -276,8 +298,9 @@ void carve(const truss_graph* g, Arena& a, Layout& L) {
   L.oeid = a.take<int32_t>(m + 1);
   L.orow = a.take<int64_t>(n + 1);
   L.perm = edges ? a.take<int32_t>(m + 1) : nullptr;
-  L.etab_n = etab_size(m);
-  L.etab = a.take<EdgeSlot>((size_t)L.etab_n);
+  L.rtab = a.take<int2>((size_t)rtab_capacity(m));
+  L.rtoff = a.take<int64_t>(n + 1);
+  L.tsz = a.take<int32_t>(n + 1);
   L.row_ptr = edges ? a.take<int64_t>(n + 1) : nullptr;
   // temporaries (could alias peeling state; kept separate for clarity)
   L.kf = a.take<int32_t>(m2 + 1);
@@ -385,15 +408,17 @@ int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStr
   dg.orow = L.orow;
   dg.ocol = L.ocol;
   dg.oeid = L.oeid;
-  // edge hash table for the membership tests of peeling
-  hipLaunchKernelGGL(k_etab_clear, dim3(grid_for(L.etab_n) < 65536 ? grid_for(L.etab_n) : 65536), dim3(kT), 0, s,
-                     L.etab, L.etab_n);
+  // row hash tables for the membership tests of peeling
+  hipLaunchKernelGGL(k_rtab_sizes, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, dg.row_ptr, n, L.tsz);
+  scan_exclusive_i32_to_i64(L.tsz, L.rtoff, n, L.stmp, s);
+  const int64_t cap = rtab_capacity(m);
+  hipLaunchKernelGGL(k_rtab_clear, dim3(grid_for(cap) < 65536 ? grid_for(cap) : 65536), dim3(kT), 0, s, L.rtab,
+                     L.rtoff, n, cap);
   if (m > 0)
-    hipLaunchKernelGGL(k_etab_insert, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.etab,
-                       (unsigned long long)(L.etab_n - 1));
+    hipLaunchKernelGGL(k_rtab_insert, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.rtoff, L.rtab);
   TRUSS_HIP(hipGetLastError());
-  dg.etab = L.etab;
-  dg.etab_mask = (unsigned long long)(L.etab_n - 1);
+  dg.rtab = L.rtab;
+  dg.rtoff = L.rtoff;
   return TRUSS_OK;
 }
 

@@ -107,40 +107,29 @@ __device__ __forceinline__ IdxT lower_bound_i32(const int* __restrict__ a, IdxT 
   return lo;
 }
 
-// ---- edge hash table ------------------------------------------------------------
+// ---- row hash tables ------------------------------------------------------------
 // The membership test of Algorithm 2 (is (v, w) an edge of E_G?) through a
-// hashtable over E_G (Section 3.2): open addressing with linear probing, key
-// (min << 32 | max), value the canonical edge id.  At most half full.
-struct EdgeSlot {
-  unsigned long long key;
-  int eid;
-  int pad;
-};
-constexpr unsigned long long kEmptyKey = ~0ULL;
+// hash table over E_G (Section 3.2), kept per vertex: the table of v holds
+// v's neighbours w with the edge id of (v, w), open addressing with linear
+// probing, 2^lg >= 2 deg(v) slots (at most half full); an empty slot has
+// w = -1.  The tables of all vertices lie back to back (offsets rtoff), so a
+// walk whose entries all look up the same vertex's neighbours touches one
+// compact region, which stays in cache, instead of lines scattered over one
+// table of all edges.
+__device__ __forceinline__ int row_table_lg(int64_t slots) { return 63 - __builtin_clzll((unsigned long long)slots); }
 
-__device__ __forceinline__ unsigned long long mix64(unsigned long long k) {
-  // MurmurHash3 64-bit finaliser
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdULL;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ULL;
-  k ^= k >> 33;
-  return k;
+__device__ __forceinline__ uint32_t row_slot(int32_t w, int lg) {
+  return lg == 0 ? 0u : ((uint32_t)w * 2654435769u) >> (32 - lg);
 }
 
-__device__ __forceinline__ unsigned long long edge_key(int a, int b) {
-  const unsigned lo = (unsigned)(a < b ? a : b), hi = (unsigned)(a < b ? b : a);
-  return ((unsigned long long)lo << 32) | hi;
-}
-
-// edge id of {a, b}, or -1 if it is not an edge
-__device__ __forceinline__ int edge_lookup(const EdgeSlot* __restrict__ tab, unsigned long long mask, int a, int b) {
-  const unsigned long long key = edge_key(a, b);
-  unsigned long long h = mix64(key) & mask;
+// edge id of (v, w) from v's table at rtab[off, off + 2^lg), or -1
+__device__ __forceinline__ int row_lookup(const int2* __restrict__ rtab, int64_t off, int lg, int32_t w) {
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = row_slot(w, lg);
   for (;;) {
-    const unsigned long long k = tab[h].key;
-    if (k == key) return tab[h].eid;
-    if (k == kEmptyKey) return -1;
+    const int2 x = rtab[off + h];
+    if (x.x == w) return x.y;
+    if (x.x < 0) return -1;
     h = (h + 1) & mask;
   }
 }

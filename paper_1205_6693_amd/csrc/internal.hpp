@@ -63,8 +63,8 @@ struct DevGraph {
   int32_t* ocol = nullptr;           // m out-neighbours, ascending
   int32_t* oeid = nullptr;           // m edge ids of oriented entries
   int32_t* perm = nullptr;           // m canonical edge -> input index (EDGES only)
-  struct EdgeSlot* etab = nullptr;   // hash table over the edges
-  unsigned long long etab_mask = 0;  // table size - 1 (a power of two >= 2m)
+  int2* rtab = nullptr;               // row hash tables (neighbour, edge id), back to back
+  const int64_t* rtoff = nullptr;    // n+1 offsets of the tables in rtab (slots; sizes are powers of two)
 };
 
 // Build: validation + canonical edge ids + symmetric and oriented CSR.

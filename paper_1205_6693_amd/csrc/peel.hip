@@ -44,7 +44,7 @@
 // known: the frontier mode (SPARSE enqueues an edge the moment its support
 // drops from k-1 to k-2, the queue of Section 3.1; DENSE re-scans the live
 // edges after every sub-round) and the membership probe (the edge
-// hash table, or binary search of the other endpoint's row).  The scheduler
+// hash table, or a binary search of the other endpoint's sorted row).  The scheduler
 // (plain, a fixed heuristic, or the learned network evaluated by the control
 // wavefront) only picks among these exact methods.
 #include "common.hpp"
@@ -131,7 +131,7 @@ struct alignas(256) PeelCtl {
   int abort;
   int launches;
   // scheduling
-  int probe;               // membership probe of the current level: 0 hash table, 1 binary search
+  int probe;               // membership probe of the current level: 0 row hash table, 1 binary search
   int sched;               // TRUSS_SCHED_* in effect
   int fix_bits, fix_vals;  // action bits fixed by the options
   int m_edges;
@@ -160,8 +160,8 @@ struct PeelArgs {
   int64_t* rec_base;
   int32_t* rec_pre;
   int32_t* rec_tot;           // per chunk of 64 positions: total walk length
-  const EdgeSlot* etab;       // edge hash table
-  unsigned long long etab_mask;
+  const int2* rtab;           // row hash tables
+  const int64_t* rtoff;
   PeelCtl* ctl;
   const float* model;         // peeling model part (learned scheduler), or null
   float* tr_feat;             // per-level trace (tr_cap rows), or null
@@ -455,10 +455,6 @@ __device__ __forceinline__ bool removed_at(int rnd, int r) { return rnd != 0 && 
 // enqueued.
 constexpr int kNI = 4;
 
-__device__ __forceinline__ ulonglong2 load_slot(const EdgeSlot* tab, unsigned long long h) {
-  return *reinterpret_cast<const ulonglong2*>(&tab[h]);
-}
-
 __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t (&e)[kNI], const int32_t (&b)[kNI],
                                                 const int64_t (&j)[kNI], bool (&ok)[kNI], int r, int l, int k,
                                                 bool sparse, int probe, int32_t (&f1)[kNI], int32_t (&f2)[kNI]) {
@@ -485,26 +481,37 @@ __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t
   }
 #pragma unroll
   for (int q = 0; q < kNI; ++q) ok[q] = ok[q] && !removed_at(s1[q], r);
-  // the second other edge (b, w): hash table or binary search
+  // the second other edge (b, w): b's row hash table, or a binary search of
+  // b's sorted row (the entries of one walk look up the same row, so they
+  // touch the same few cached lines either way)
   if (probe == 0) {
-    unsigned long long key[kNI], h[kNI];
-    ulonglong2 sl[kNI];
+    const int2* tb[kNI];
+    uint32_t h[kNI], mask[kNI];
+    int2 sl[kNI];
 #pragma unroll
-    for (int q = 0; q < kNI; ++q) {
-      key[q] = edge_key(b[q], w[q]);
-      h[q] = mix64(key[q]) & P.etab_mask;
-      sl[q] = make_ulonglong2(kEmptyKey, 0ULL);
-      if (ok[q]) sl[q] = load_slot(P.etab, h[q]);
+    for (int q = 0; q < kNI; ++q) {  // the first slots of all lookups in flight together
+      tb[q] = P.rtab;
+      h[q] = 0;
+      mask[q] = 0;
+      sl[q] = make_int2(-1, 0);
+      if (ok[q]) {
+        const int64_t off = P.rtoff[b[q]];
+        const int lg = row_table_lg(P.rtoff[b[q] + 1] - off);
+        tb[q] = P.rtab + off;
+        mask[q] = (1u << lg) - 1u;
+        h[q] = row_slot(w[q], lg);
+        sl[q] = tb[q][h[q]];
+      }
     }
 #pragma unroll
     for (int q = 0; q < kNI; ++q) {
       if (!ok[q]) continue;
-      while (sl[q].x != key[q] && sl[q].x != kEmptyKey) {
-        h[q] = (h[q] + 1) & P.etab_mask;
-        sl[q] = load_slot(P.etab, h[q]);
+      while (sl[q].x != w[q] && sl[q].x >= 0) {
+        h[q] = (h[q] + 1) & mask[q];
+        sl[q] = tb[q][h[q]];
       }
-      if (sl[q].x == key[q]) e2[q] = (int32_t)(uint32_t)sl[q].y;
-      else ok[q] = false;
+      e2[q] = sl[q].y;
+      ok[q] = sl[q].x == w[q];
     }
   } else {
 #pragma unroll
@@ -1130,8 +1137,8 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
   P.rec_pre = L.rec_pre;
   P.rec_base = L.rec_base;
   P.rec_tot = L.rec_tot;
-  P.etab = dg.etab;
-  P.etab_mask = dg.etab_mask;
+  P.rtab = dg.rtab;
+  P.rtoff = dg.rtoff;
   P.ctl = L.ctl;
   P.model = plan.sched == TRUSS_SCHED_LEARNED ? plan.model : nullptr;
   P.tr_cap = trace && trace->level_feat && trace->level_ms && trace->level_action ? trace->level_cap : 0;
