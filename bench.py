@@ -149,10 +149,14 @@ def edge_work_model(n, s, d):
             "sum_min_deg_log": int((mn * lg).sum())}
 
 
-def method_bytes(model, m, triangles):
-    """Algorithmic bytes of support and peeling for the method (see main)."""
+def method_bytes(model, m, triangles, probe="hash"):
+    """Algorithmic bytes of support and peeling for the method (see main).
+    The membership test of each walked entry is priced as the method keeps
+    E_G: one 16-byte hash-table slot (Section 3.2), or, with probe="bsearch",
+    4 bytes per step of a binary search of the longer row."""
     sup = 4 * model["merge_elems"] + 16 * triangles + 20 * m
-    peel = 16 * m + 8 * model["sum_min_deg"] + 4 * model["sum_min_deg_log"] + 8 * triangles + 4 * m + 8 * m
+    probes = 16 * model["sum_min_deg"] if probe == "hash" else 4 * model["sum_min_deg_log"]
+    peel = 16 * m + 8 * model["sum_min_deg"] + probes + 8 * triangles + 4 * m + 8 * m
     return sup, peel
 
 
@@ -543,11 +547,12 @@ def main():
     # algorithmic bytes: the per-unit figures of the byte model for the method
     # (support, merge form: 4 B per list element compared, 16 B per triangle,
     # 20 B per edge; peeling: per edge 16 B + 8 B per entry of the smaller
-    # endpoint's row + 4 B per binary-search step of its probes, 8 B per
+    # endpoint's row + one 16 B hash-table slot per membership test, 8 B per
     # triangle, 4 B truss and 8 B of frontier per edge), and beside them the
-    # bytes of what the kernels walk here (after row compaction, hash probes)
+    # bytes of what the kernels walk here (after row compaction)
     T3 = st["triangles"]
     sup_bytes, peel_bytes = method_bytes(model, m, T3)
+    _, peel_bytes_bs = method_bytes(model, m, T3, probe="bsearch")
     sup_walked = 4 * model["support_pairs"] + 24 * model["oriented_edges"] + 8 * T3
     peel_walked = 16 * st["peel_work"] + 44 * m
     kernels = {
@@ -563,6 +568,9 @@ def main():
     traffic = measured_traffic(args.workload, kd["name"], kd["launches"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kd["name"],
+                "traffic_GBs": round(traffic / (kd["ms"] / kd["launches"] * 1e-3) / 1e9, 2) if traffic else None,
+                "traffic_frac": round(traffic / (kd["ms"] / kd["launches"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+                if traffic else None,
                 "launches_per_step": kd["launches"], "avg_launch_ms": round(kd["ms"] / kd["launches"], 4),
                 "bytes_per_launch": int(kd["bytes"] / kd["launches"]),
                 "achieved_walked": round(walked, 2), "frac_walked": round(walked / HBM_PEAK_GBS, 5),
@@ -587,6 +595,7 @@ def main():
                              "bytes": v["bytes"], "walked_GB/s": round(v["walked"] / (v["ms"] * 1e-3) / 1e9, 2),
                              "walked_bytes": v["walked"]} for k, v in kernels.items()},
         "peel_kernel_ms": ms_peel_kernel,
+        "peel_bytes_bsearch_probes": peel_bytes_bs,
     }
     forms = {args.scheduler: {"edges_per_s": result["value"], "ms_per_step": ms_per_step, "steps": args.steps,
                               "warmup": args.warmup, "verified": verified}}

@@ -59,7 +59,10 @@ def test_models_agree_on_rmat():
         assert c[k] == e[k], k
     sup, peel = bench.method_bytes(e, s.size, 1000)
     assert sup == 4 * e["merge_elems"] + 16 * 1000 + 20 * s.size
-    assert peel == 28 * s.size + 8 * e["sum_min_deg"] + 4 * e["sum_min_deg_log"] + 8 * 1000
+    # one 16-byte hash-table slot per membership test (the method's E_G)
+    assert peel == 28 * s.size + 8 * e["sum_min_deg"] + 16 * e["sum_min_deg"] + 8 * 1000
+    _, peel_bs = bench.method_bytes(e, s.size, 1000, probe="bsearch")
+    assert peel_bs == 28 * s.size + 8 * e["sum_min_deg"] + 4 * e["sum_min_deg_log"] + 8 * 1000
 
 
 def test_traffic_lookup_needs_matching_sources(tmp_path, monkeypatch):
