@@ -376,6 +376,26 @@ int truss_decompose_traced(const truss_graph *g, int32_t *truss_out, const truss
                            truss_stats *stats, truss_trace *trace, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* ---- decomposition without allocation ------------------------------------ */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * decomposition as truss_decompose (same kernels, same output), with its
+ * scratch taken from a fixed device array of TRUSS_NOALLOC_SCRATCH_BYTES
+ * bytes instead of a caller workspace.  Each GPU the library runs on holds
+ * one such array from its first call on that GPU until the process ends.
+ *   g, truss_out, opts: as for truss_decompose.
+ *   stats (host, nullable): as for truss_decompose, except that every time
+ *     field is 0 (no timing events are created).
+ * Graphs whose truss_workspace_size exceeds the array are refused with
+ * TRUSS_E_WORKSPACE before any device work.  The call allocates nothing: no
+ * hipMalloc, hipFree, events or streams.  Every call on one GPU uses that
+ * GPU's array and leaves its contents behind; calls that overlap on one GPU
+ * (two threads, or two streams of one thread) race and give undefined
+ * results. */
+#define TRUSS_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int truss_decompose_noalloc(const truss_graph *g, int32_t *truss_out, const truss_options *opts,
+                            truss_stats *stats, void *stream);
+
 /* ---- learned scheduler: the network and its training ----------------- */
 /* Two-layer perceptron y = W2 tanh(W1 x + b1) + b2 in fp32.  params packs
  * W1[H][F], b1[H], W2[O][H], b2[O], row-major; X is B x F and Y is B x O,

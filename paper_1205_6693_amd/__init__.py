@@ -6,6 +6,8 @@ the library's HIP kernels.  PyTorch supplies device memory and the stream.
 Entry points mirror the C ABI in include/truss.h:
     truss_support(graph)              -> (sup int32[m] cuda tensor, triangles)
     truss_decompose(graph, ...)       -> (truss int32[m] cuda tensor, stats dict)
+    truss_decompose_noalloc(graph, out, ...) -> (out, stats dict), scratch in a fixed
+                                         device array (callers that cannot allocate)
     truss_batch(vtx_off, edge_off, src, dst, ...) -> (truss int32[M], stats dict)
     truss_workspace_size(graph)       -> bytes
     truss_decompose_traced(graph, ...) -> (truss, stats, trace dict)
@@ -138,6 +140,7 @@ def load_library():
     lib.truss_workspace_size.argtypes = [gp, op, ctypes.POINTER(ctypes.c_size_t)]
     lib.truss_support.argtypes = [gp, vp, ctypes.POINTER(i64), vp, ctypes.c_size_t, vp]
     lib.truss_decompose.argtypes = [gp, vp, op, sp, vp, ctypes.c_size_t, vp]
+    lib.truss_decompose_noalloc.argtypes = [gp, vp, op, sp, vp]
     lib.truss_batch_workspace_size.argtypes = [i32, vp, vp, op, ctypes.POINTER(ctypes.c_size_t)]
     lib.truss_batch.argtypes = [i32, vp, vp, vp, vp, vp, op, sp, vp, ctypes.c_size_t, vp]
     lib.truss_batch_plan_create.argtypes = [i32, vp, vp, vp, vp, vp, op, vp, ctypes.c_size_t, vp,
@@ -363,6 +366,25 @@ def truss_decompose(graph: Graph, opts: Options | None = None, out=None, ws=None
     with _on(graph.device, stream) as s_:
         _check(lib.truss_decompose(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
                                    ctypes.byref(st), _ptr(ws), _ws_bytes(ws, graph.device), s_))
+    return out, st.to_dict()
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def truss_decompose_noalloc(graph: Graph, out, opts: Options | None = None, stream=None):
+    """truss_decompose with its scratch in the library's fixed device array
+    (no workspace, no allocation inside the call; graphs needing more than
+    NOALLOC_SCRATCH_BYTES of scratch are refused).  out: caller's int32[m]
+    CUDA tensor.  Calls that overlap on one GPU race."""
+    torch = _torch()
+    lib = load_library()
+    _dev(out, "out", torch.int32, graph.m, graph.device)
+    st = Stats()
+    g = graph._c()
+    with _on(graph.device, stream) as s_:
+        _check(lib.truss_decompose_noalloc(ctypes.byref(g), _ptr(out), ctypes.byref(opts) if opts else None,
+                                           ctypes.byref(st), s_))
     return out, st.to_dict()
 
 

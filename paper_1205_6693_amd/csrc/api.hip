@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -220,7 +221,7 @@ struct Timer {
 // sub (nullable): the neighbourhood-subgraph extras of run_subgraph (decompose mode)
 int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles,
                const truss_options* opts_in, truss_stats* stats, void* ws, size_t ws_bytes, hipStream_t s,
-               truss_trace* trace, const SubgraphRun* sub = nullptr) {
+               truss_trace* trace, const SubgraphRun* sub = nullptr, bool timed = true) {
   int rc = check_graph(g);
   if (rc) return rc;
   rc = validate_options(opts_in);
@@ -253,7 +254,8 @@ int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles
   PeelPlan pp;
   int fallback = 0;
   resolve(opts_in, &sp, &pp, &fallback, s);
-  Timer tm(stats != nullptr, s);
+  pp.timed = timed;
+  Timer tm(stats != nullptr && timed, s);
   tm.mark(0);
   DevGraph dg;
   rc = build_graph(g, a, dg, p.d_err, s);
@@ -889,6 +891,41 @@ int device_grid_blocks(const void* kernel, int block, size_t lds) {
 
 using namespace truss;
 
+// ---- scratch of truss_decompose_noalloc ---------------------------------------------------
+// A fixed device array (one per GPU, held until the process ends) for callers
+// that cannot allocate.  Host code never passes the array's name to a kernel:
+// it looks up the device address once per device and uses that.
+static __device__ __align__(256) unsigned char scratch[TRUSS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, found once per
+// device with that device current.
+int scratch_address(void** out) {
+  int dev = -1;
+  TRUSS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_last_error("device %d is beyond the %d devices the scratch table covers", dev, kMaxDevices);
+    return TRUSS_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_last_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return TRUSS_E_DEVICE;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return TRUSS_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void truss_default_options(truss_options* o) {
@@ -926,6 +963,29 @@ int truss_decompose(const truss_graph* g, int32_t* truss_out, const truss_option
                     void* ws, size_t ws_bytes, void* stream) {
   if (g && g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
   return run_single(g, kModeDecompose, truss_out, nullptr, opts, stats, ws, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+int truss_decompose_noalloc(const truss_graph* g, int32_t* truss_out, const truss_options* opts, truss_stats* stats,
+                            void* stream) {
+  int rc = check_graph(g);
+  if (rc) return rc;
+  rc = validate_options(opts);
+  if (rc) return rc;
+  if (g->m > 0 && !truss_out) { set_last_error("truss_out is NULL"); return TRUSS_E_INVAL; }
+  Arena need;
+  need.counting = true;
+  Plan dummy;
+  layout(g, need, dummy, nullptr);
+  if (need.used > TRUSS_NOALLOC_SCRATCH_BYTES) {
+    set_last_error("graph needs %zu bytes of scratch; the fixed array holds %zu", need.used,
+                   (size_t)TRUSS_NOALLOC_SCRATCH_BYTES);
+    return TRUSS_E_WORKSPACE;
+  }
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  return run_single(g, kModeDecompose, truss_out, nullptr, opts, stats, ws, TRUSS_NOALLOC_SCRATCH_BYTES,
+                    (hipStream_t)stream, nullptr, nullptr, false);
 }
 
 int truss_decompose_traced(const truss_graph* g, int32_t* truss_out, const truss_options* opts, truss_stats* stats,

@@ -88,6 +88,7 @@ struct PeelPlan {
   int grid_blocks = 0;
   int first_level = 2;  // the first level peeled takes every live edge with sup <= first_level - 2
   int stop_level = 0;   // > 0: stop once the next level would exceed it (later edges keep no truss number)
+  bool timed = true;    // time the kernel's launches with HIP events
 };
 
 // Support: sr[e].x = sup(e) for every canonical edge (sr must be zeroed inside).

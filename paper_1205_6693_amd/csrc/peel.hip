@@ -1148,7 +1148,7 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
   PeelCtl h;
   int launches = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  const bool timed = hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
+  const bool timed = plan.timed && hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
   double kernel_ms = 0.0;
   for (;;) {
     if (timed) (void)hipEventRecord(ev0, s);

@@ -270,3 +270,15 @@ def test_missing_library_fails_loudly(tmp_path):
             "try:\n    T.load_library()\nexcept ImportError as e:\n    print('raised', e)\n" % str(tmp_path / "none.so"))
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=120)
     assert "raised" in r.stdout and "not built" in r.stdout, r.stdout + r.stderr
+
+
+def test_noalloc_refuses_oversized_graph_without_device_work(T):
+    """truss_decompose_noalloc checks the graph's scratch need against its
+    fixed array before touching a device (so this runs without a GPU)."""
+    lib = T.load_library()
+    st = T.Stats()
+    rc = lib.truss_decompose_noalloc(ctypes.byref(_graph(T, 1 << 20, 4 << 20)), ctypes.c_void_p(4096), None,
+                                     ctypes.byref(st), None)
+    assert rc == T.E_WORKSPACE
+    assert b"fixed array" in lib.truss_last_error()
+    assert lib.truss_decompose_noalloc(None, None, None, None, None) == T.E_INVAL
