@@ -165,6 +165,8 @@ def method_bytes(model, m, triangles, probe="hash"):
 _DIGEST_FILES = {
     "k_peel": ["csrc/peel.hip", "csrc/common.hpp", "csrc/internal.hpp", "csrc/mlp.hpp", "csrc/build.hip",
                "csrc/scan.hip", "csrc/support.hip", "csrc/api.hip", "sched_model.json"],
+    "k_sup": ["csrc/support.hip", "csrc/common.hpp", "csrc/internal.hpp", "csrc/mlp.hpp", "csrc/build.hip",
+              "csrc/scan.hip", "csrc/api.hip", "sched_model.json"],
     "k_batch": ["csrc/batch.hip", "csrc/common.hpp", "csrc/internal.hpp", "csrc/api.hip"],
 }
 
@@ -207,6 +209,15 @@ def measured_traffic(workload, kernel, launches):
         return None
 
 
+def traffic_fields(traffic, launch_ms):
+    """Counter-measured bytes per launch, and the bandwidth they give over the
+    launch time, when a record exists."""
+    if not traffic:
+        return {"traffic": None}
+    gbs = traffic / (launch_ms * 1e-3) / 1e9
+    return {"traffic": traffic, "traffic_GB/s": round(gbs, 2), "traffic_frac": round(gbs / HBM_PEAK_GBS, 5)}
+
+
 def calibrate_copy(nbytes):
     """A plain device copy of known size, for scaling the PMC byte counters."""
     import torch
@@ -236,9 +247,8 @@ def summarize_db(path):
     for name, calls, tot, avg in rows:
         out.append("  %-60s calls=%d total_ns=%d avg_ns=%.0f" % (_short(name)[:60], calls, tot, avg))
     try:
-        cnt = c.execute("select k.name, p.counter_name, count(distinct p.dispatch_id), sum(p.value) "
-                        "from counters_collection p join kernels k on k.dispatch_id = p.dispatch_id "
-                        "group by k.name, p.counter_name").fetchall()
+        cnt = c.execute("select kernel_name, counter_name, count(distinct dispatch_id), sum(value) "
+                        "from counters_collection group by kernel_name, counter_name").fetchall()
     except sqlite3.Error:
         cnt = []
     if cnt:
@@ -557,7 +567,7 @@ def main():
     peel_walked = 16 * st["peel_work"] + 44 * m
     kernels = {
         "support": {"bytes": sup_bytes, "walked": sup_walked, "ms": ms_sup, "launches": 1,
-                    "name": "support kernels"},
+                    "name": "k_sup"},
         "peel": {"bytes": peel_bytes, "walked": peel_walked, "ms": ms_peel_kernel, "launches": launches,
                  "name": "k_peel"},
     }
@@ -591,9 +601,14 @@ def main():
         "heavy_rounds": st["heavy_rounds"], "frontier_hist": st["frontier_hist"],
         "peel_phase_ms": dict(zip(["sweep", "start", "rounds", "pieces", "dense"], st["ms_phase"][:5])),
         "roofline": roofline,
-        "roofline_all": {k: {"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2), "ms": round(v["ms"], 3),
-                             "bytes": v["bytes"], "walked_GB/s": round(v["walked"] / (v["ms"] * 1e-3) / 1e9, 2),
-                             "walked_bytes": v["walked"]} for k, v in kernels.items()},
+        "roofline_all": {k: dict({"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 2), "ms": round(v["ms"], 3),
+                                  "frac": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                                  "bytes": v["bytes"],
+                                  "walked_GB/s": round(v["walked"] / (v["ms"] * 1e-3) / 1e9, 2),
+                                  "walked_bytes": v["walked"]},
+                                 **traffic_fields(measured_traffic(args.workload, v["name"], v["launches"]),
+                                                  v["ms"] / v["launches"]))
+                         for k, v in kernels.items()},
         "peel_kernel_ms": ms_peel_kernel,
         "peel_bytes_bsearch_probes": peel_bytes_bs,
     }
