@@ -180,9 +180,9 @@ void take_bound(const truss_graph* g, Arena& a, Plan& p) {
 void layout(const truss_graph* g, Arena& a, Plan& p, DevGraph* dg_for_sizes) {
   p.d_err = a.take<int>(64);
   p.d_total = a.take<unsigned long long>(8);
-  build_workspace(g, a);
+  build_workspace(g, a, true);
   p.sr = a.take<int2>((size_t)g->m + 1);
-  p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
+  p.truss_canon = a.take<int32_t>((size_t)g->m + 1);
   take_bound(g, a, p);
   DevGraph dg;
   dg.n = g->n;
@@ -258,11 +258,11 @@ int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles
   Timer tm(stats != nullptr && timed, s);
   tm.mark(0);
   DevGraph dg;
-  rc = build_graph(g, a, dg, p.d_err, s);
+  rc = build_graph(g, a, dg, p.d_err, s, true);
   if (rc) return rc;
   tm.mark(1);
   p.sr = a.take<int2>((size_t)g->m + 1);
-  p.truss_canon = g->fmt == TRUSS_FMT_EDGES ? a.take<int32_t>((size_t)g->m + 1) : nullptr;
+  p.truss_canon = a.take<int32_t>((size_t)g->m + 1);
   take_bound(g, a, p);
   rc = compute_support(dg, sp, p.sr, a, s, trace);
   if (rc) return rc;
@@ -289,7 +289,7 @@ int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles
     tm.mark(3);
   } else {
     if (stats && g->m > 0) hipLaunchKernelGGL(k_sum_sup, dim3(1024), dim3(kT), 0, s, p.sr, g->m, p.d_total);
-    int32_t* tc = g->fmt == TRUSS_FMT_EDGES ? p.truss_canon : out;
+    int32_t* tc = dg.perm ? p.truss_canon : out;
     if (sub && g->m > 0) {
       if (sub->sup_out)
         hipLaunchKernelGGL(k_scatter_sup, dim3(grid_for(g->m)), dim3(kT), 0, s, p.sr, dg.perm, g->m, sub->sup_out,
@@ -302,7 +302,7 @@ int run_single(const truss_graph* g, Mode mode, int32_t* out, int64_t* triangles
     }
     rc = peel(dg, pp, p.sr, tc, a, &pr, s, trace);
     if (rc) return rc;
-    if (g->fmt == TRUSS_FMT_EDGES && g->m > 0)
+    if (dg.perm && g->m > 0)
       hipLaunchKernelGGL(k_scatter_out, dim3(grid_for(g->m)), dim3(kT), 0, s, tc, dg.perm, g->m, out);
     tm.mark(3);
     TRUSS_HIP(hipGetLastError());

@@ -110,6 +110,56 @@ __global__ void k_sym_lower(const uint32_t* __restrict__ tkey, const int32_t* __
   kf[pos] = vertex_before(deg_of(row_ptr, v), v, deg_of(row_ptr, u), u) ? 1 : 0;
 }
 
+// ---- locality relabelling ------------------------------------------------------------
+// Vertices are renumbered by (degree, id) ascending before the graph is built:
+// the orientation order of triangle listing becomes the id order, and the edges
+// among high-degree vertices -- the ones the late levels of peeling walk over
+// and over -- get the highest canonical ids, so that their supports, stamps and
+// rows share lines and stay in cache.  perm maps each relabelled edge back to
+// the caller's edge (input pair, or canonical CSR position), so outputs keep
+// the caller's order.
+
+// edge-list input: range and self-loop checks, degrees over the valid pairs
+__global__ void k_edge_degrees(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t m,
+                               int32_t n, int32_t* __restrict__ deg, int* err) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t u = src[i], v = dst[i];
+  if (u < 0 || u >= n || v < 0 || v >= n) { report(err, kErrRange); return; }
+  if (u == v) { report(err, kErrSelfloop); return; }
+  atomicAdd(&deg[u], 1);
+  atomicAdd(&deg[v], 1);
+}
+
+// sort keys (degree, id) of the vertices; degrees from the CSR offsets or from deg
+__global__ void k_degree_keys(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ deg, int32_t n, int vb,
+                              uint64_t* __restrict__ key, int32_t* __restrict__ val) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int64_t d = row_ptr ? row_ptr[v + 1] - row_ptr[v] : deg[v];
+  const int64_t dmax = (1LL << vb) - 1;  // a simple graph has d < n <= 2^vb; larger only on invalid input
+  d = d < 0 ? 0 : d > dmax ? dmax : d;
+  key[v] = ((uint64_t)d << vb) | (uint64_t)v;
+  val[v] = (int32_t)v;
+}
+
+__global__ void k_ranks(const int32_t* __restrict__ order, int32_t n, int32_t* __restrict__ rank) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) rank[order[i]] = (int32_t)i;
+}
+
+// canonical keys of the relabelled edges (ids already checked)
+__global__ void k_canon_relabel(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t m, int vb,
+                                const int32_t* __restrict__ rank, uint64_t* __restrict__ key,
+                                int32_t* __restrict__ val) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t u = rank[src[i]], v = rank[dst[i]];
+  const uint64_t a = (uint64_t)(u < v ? u : v), b = (uint64_t)(u < v ? v : u);
+  key[i] = (a << vb) | b;
+  val[i] = (int32_t)i;
+}
+
 // ---- CSR input -------------------------------------------------------------------------
 
 __global__ void k_rowptr_check(const int64_t* __restrict__ row_ptr, int32_t n, int64_t m2, int* err) {
@@ -285,11 +335,16 @@ struct Layout {
   int2* rtab;
   int64_t* rtoff;
   int32_t* tsz;
+  // relabelling: vertex sort keys and values (ping-pong), their radix scratch, ranks, degrees
+  uint64_t *vkey, *vkey_alt;
+  int32_t *vval, *vval_alt, *vtmp, *rank, *vdeg;
 };
 
-void carve(const truss_graph* g, Arena& a, Layout& L) {
+void carve(const truss_graph* g, bool relabel, Arena& a, Layout& L) {
   const int64_t n = g->n, m = g->m, m2 = 2 * m;
-  const bool edges = g->fmt == TRUSS_FMT_EDGES;
+  // the edge-list build runs for edge-list input and, after validation, for
+  // relabelled CSR input
+  const bool edges = g->fmt == TRUSS_FMT_EDGES || relabel;
   L.col = a.take<int32_t>(m2 + 1);
   L.seid = a.take<int32_t>(m2 + 1);
   L.eu = a.take<int32_t>(m + 1);
@@ -316,7 +371,7 @@ void carve(const truss_graph* g, Arena& a, Layout& L) {
     L.uppre = a.take<int64_t>(n + 1);
     L.lowpre = a.take<int64_t>(n + 1);
     L.rtmp = a.take<int32_t>(radix_tmp_elems(m + 1));
-    L.rowid = nullptr;
+    L.rowid = g->fmt == TRUSS_FMT_CSR ? a.take<int32_t>(m2 + 1) : nullptr;
   } else {
     L.rowid = a.take<int32_t>(m2 + 1);
     L.key = L.key_alt = nullptr;
@@ -325,50 +380,86 @@ void carve(const truss_graph* g, Arena& a, Layout& L) {
     L.uppre = L.lowpre = nullptr;
     L.rtmp = nullptr;
   }
+  if (relabel) {
+    L.vkey = a.take<uint64_t>(n + 1);
+    L.vkey_alt = a.take<uint64_t>(n + 1);
+    L.vval = a.take<int32_t>(n + 1);
+    L.vval_alt = a.take<int32_t>(n + 1);
+    L.vtmp = a.take<int32_t>(radix_tmp_elems(n + 1));
+    L.rank = a.take<int32_t>(n + 1);
+    L.vdeg = a.take<int32_t>(n + 1);
+  } else {
+    L.vkey = L.vkey_alt = nullptr;
+    L.vval = L.vval_alt = L.vtmp = L.rank = L.vdeg = nullptr;
+  }
+}
+
+// ranks of the vertices in (degree, id) order; degrees from row_ptr, else from deg
+void degree_ranks(const int64_t* row_ptr, const int32_t* deg, int32_t n, int vb, Layout& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, row_ptr, deg, n, vb, L.vkey,
+                     L.vval);
+  radix_sort_u64(L.vkey, L.vval, L.vkey_alt, L.vval_alt, n, 2 * vb, L.vtmp, s);
+  hipLaunchKernelGGL(k_ranks, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, L.vval, n, L.rank);
+}
+
+// symmetric CSR, canonical edges and perm from the unsorted canonical keys in
+// L.key / L.val (val: the caller's index of each edge)
+int rows_from_keys(int32_t n, int64_t m, int vb, Layout& L, int* d_err, hipStream_t s) {
+  radix_sort_u64(L.key, L.val, L.key_alt, L.val_alt, m, 2 * vb, L.rtmp, s);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.upcnt, (int64_t)n + 1, 0);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.lowcnt, (int64_t)n + 1, 0);
+  hipLaunchKernelGGL(k_edges_from_keys, dim3(grid_for(m)), dim3(kT), 0, s, L.key, L.val, m, vb, L.eu, L.ev, L.perm,
+                     L.upcnt, L.lowcnt, d_err);
+  const int rc = read_err(d_err, s);
+  if (rc) return rc;
+  scan_exclusive_i32_to_i64(L.upcnt, L.uppre, n, L.stmp, s);
+  scan_exclusive_i32_to_i64(L.lowcnt, L.lowpre, n, L.stmp, s);
+  hipLaunchKernelGGL(k_rowptr_sum, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.uppre, L.lowpre, n, L.row_ptr);
+  hipLaunchKernelGGL(k_sym_upper, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.row_ptr, L.lowcnt, L.uppre,
+                     L.col, L.seid, L.kf);
+  // lower halves of the rows: stable sort of the canonical order by the larger endpoint
+  uint32_t* tkey = reinterpret_cast<uint32_t*>(L.key);
+  uint32_t* tkey_alt = reinterpret_cast<uint32_t*>(L.key_alt);
+  hipLaunchKernelGGL(k_copy_ev, dim3(grid_for(m)), dim3(kT), 0, s, L.ev, m, tkey, L.val);
+  radix_sort_u32(tkey, L.val, tkey_alt, L.val_alt, m, vb, L.rtmp, s);
+  hipLaunchKernelGGL(k_sym_lower, dim3(grid_for(m)), dim3(kT), 0, s, tkey, L.val, m, L.row_ptr, L.lowpre, L.eu,
+                     L.col, L.seid, L.kf);
+  return TRUSS_OK;
 }
 
 }  // namespace
 
-size_t build_workspace(const truss_graph* g, Arena& a) {
+size_t build_workspace(const truss_graph* g, Arena& a, bool relabel) {
   Layout L;
-  carve(g, a, L);
+  carve(g, relabel, a, L);
   return a.used;
 }
 
-int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStream_t s) {
+int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStream_t s, bool relabel) {
   Layout L;
-  carve(g, a, L);
+  carve(g, relabel, a, L);
   if (a.overflow()) return TRUSS_E_WORKSPACE;
   const int32_t n = g->n;
   const int64_t m = g->m, m2 = 2 * m;
+  const int vb = bits_for(n) > 0 ? bits_for(n) : 1;
   dg.n = n;
   dg.m = m;
   hipLaunchKernelGGL(k_init_err, dim3(1), dim3(1), 0, s, d_err);
 
   if (g->fmt == TRUSS_FMT_EDGES) {
-    const int vb = bits_for(n) > 0 ? bits_for(n) : 1;
-    hipLaunchKernelGGL(k_canon, dim3(grid_for(m)), dim3(kT), 0, s, g->src, g->dst, m, n, vb, L.key, L.val, d_err);
-    int rc = read_err(d_err, s);
-    if (rc) return rc;
-    radix_sort_u64(L.key, L.val, L.key_alt, L.val_alt, m, 2 * vb, L.rtmp, s);
-    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.upcnt, (int64_t)n + 1, 0);
-    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.lowcnt, (int64_t)n + 1, 0);
-    hipLaunchKernelGGL(k_edges_from_keys, dim3(grid_for(m)), dim3(kT), 0, s, L.key, L.val, m, vb, L.eu, L.ev,
-                       L.perm, L.upcnt, L.lowcnt, d_err);
-    rc = read_err(d_err, s);
-    if (rc) return rc;
-    scan_exclusive_i32_to_i64(L.upcnt, L.uppre, n, L.stmp, s);
-    scan_exclusive_i32_to_i64(L.lowcnt, L.lowpre, n, L.stmp, s);
-    hipLaunchKernelGGL(k_rowptr_sum, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.uppre, L.lowpre, n, L.row_ptr);
-    hipLaunchKernelGGL(k_sym_upper, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.row_ptr, L.lowcnt,
-                       L.uppre, L.col, L.seid, L.kf);
-    // lower halves of the rows: stable sort of the canonical order by the larger endpoint
-    uint32_t* tkey = reinterpret_cast<uint32_t*>(L.key);
-    uint32_t* tkey_alt = reinterpret_cast<uint32_t*>(L.key_alt);
-    hipLaunchKernelGGL(k_copy_ev, dim3(grid_for(m)), dim3(kT), 0, s, L.ev, m, tkey, L.val);
-    radix_sort_u32(tkey, L.val, tkey_alt, L.val_alt, m, vb, L.rtmp, s);
-    hipLaunchKernelGGL(k_sym_lower, dim3(grid_for(m)), dim3(kT), 0, s, tkey, L.val, m, L.row_ptr, L.lowpre, L.eu,
-                       L.col, L.seid, L.kf);
+    int rc;
+    if (relabel) {
+      hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.vdeg, (int64_t)n + 1, 0);
+      hipLaunchKernelGGL(k_edge_degrees, dim3(grid_for(m)), dim3(kT), 0, s, g->src, g->dst, m, n, L.vdeg, d_err);
+      if ((rc = read_err(d_err, s))) return rc;
+      degree_ranks(nullptr, L.vdeg, n, vb, L, s);
+      hipLaunchKernelGGL(k_canon_relabel, dim3(grid_for(m)), dim3(kT), 0, s, g->src, g->dst, m, vb, L.rank, L.key,
+                         L.val);
+    } else {
+      hipLaunchKernelGGL(k_canon, dim3(grid_for(m)), dim3(kT), 0, s, g->src, g->dst, m, n, vb, L.key, L.val, d_err);
+      if ((rc = read_err(d_err, s))) return rc;
+    }
+    if ((rc = rows_from_keys(n, m, vb, L, d_err, s))) return rc;
     dg.row_ptr = L.row_ptr;
     dg.perm = L.perm;
   } else {
@@ -393,8 +484,19 @@ int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStr
                        L.seid, L.kf, d_err);
     rc = read_err(d_err, s);
     if (rc) return rc;
-    dg.row_ptr = g->row_ptr;
-    dg.perm = nullptr;
+    if (relabel) {
+      // the validated canonical edges, renamed, go through the edge-list build;
+      // perm then maps each edge to its canonical CSR position
+      degree_ranks(g->row_ptr, nullptr, n, vb, L, s);
+      hipLaunchKernelGGL(k_canon_relabel, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, vb, L.rank, L.key,
+                         L.val);
+      if ((rc = rows_from_keys(n, m, vb, L, d_err, s))) return rc;
+      dg.row_ptr = L.row_ptr;
+      dg.perm = L.perm;
+    } else {
+      dg.row_ptr = g->row_ptr;
+      dg.perm = nullptr;
+    }
   }
   // oriented CSR: stable compaction of the symmetric rows by the orientation flag
   scan_exclusive_i32_to_i64(L.kf, L.opos, m2, L.stmp, s);

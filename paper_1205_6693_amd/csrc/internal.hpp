@@ -70,8 +70,11 @@ struct DevGraph {
 // Build: validation + canonical edge ids + symmetric and oriented CSR.
 // Returns TRUSS_OK or a TRUSS_E_* code; syncs on the stream for the checks.
 struct BuildBufs;
-size_t build_workspace(const truss_graph* g, Arena& a);
-int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStream_t s);
+// relabel: vertices renumbered by (degree, id) inside the build (dg.perm then
+// always maps the build's edges to the caller's); off where the caller reads
+// vertex ids back out of dg
+size_t build_workspace(const truss_graph* g, Arena& a, bool relabel = false);
+int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStream_t s, bool relabel = false);
 
 // Scheduling of the exact methods (the scheduler never changes results).
 struct SupPlan {

@@ -60,11 +60,11 @@ constexpr int kWaves = kT / kWave;
 // adjacency entries per segment of a chunk's walks: smaller segments spread
 // mid-size rounds over more workgroups, larger ones cut the announcement
 // traffic of rounds with big frontiers
-constexpr int kSegSmall = 2 * 1024, kSegLarge = 4 * 1024;
+constexpr int kSegSmall = 1 * 1024, kSegLarge = 8 * 1024;
 constexpr int kSegLargeFrontier = 8192;  // frontiers of at least this many edges use kSegLarge
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kHistBins = 6;
-constexpr long long kCompactNum = 7, kCompactDen = 10;  // row compaction threshold
+constexpr long long kCompactNum = 8, kCompactDen = 10;  // row compaction threshold
 constexpr int kStageA = 8192;  // LDS staging of live-list appends (entries)
 constexpr int kStageQ = 2048;  // LDS staging of frontier-queue appends
 constexpr int kMinChunk = 64;  // smallest frontier chunk
