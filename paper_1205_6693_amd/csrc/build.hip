@@ -50,38 +50,46 @@ __global__ void k_canon(const int32_t* __restrict__ src, const int32_t* __restri
   val[i] = (int32_t)i;
 }
 
+__device__ __forceinline__ int64_t deg_of(const int64_t* __restrict__ rp, int32_t v) { return rp[v + 1] - rp[v]; }
+
 __global__ void k_edges_from_keys(const uint64_t* __restrict__ key, const int32_t* __restrict__ val, int64_t m,
                                   int vb, int32_t* __restrict__ eu, int32_t* __restrict__ ev,
-                                  int32_t* __restrict__ perm, int32_t* __restrict__ upcnt,
-                                  int32_t* __restrict__ lowcnt, int* err) {
+                                  int32_t* __restrict__ perm, int* err) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= m) return;
   uint64_t k = key[e];
   if (e > 0 && key[e - 1] == k) report(err, kErrDup);
-  int32_t u = (int32_t)(k >> vb), v = (int32_t)(k & ((1ULL << vb) - 1));
-  eu[e] = u;
-  ev[e] = v;
+  eu[e] = (int32_t)(k >> vb);
+  ev[e] = (int32_t)(k & ((1ULL << vb) - 1));
   perm[e] = val[e];
-  atomicAdd(&upcnt[u], 1);
-  atomicAdd(&lowcnt[v], 1);
 }
 
-__global__ void k_rowptr_sum(const int64_t* __restrict__ a, const int64_t* __restrict__ b, int32_t n,
-                             int64_t* __restrict__ out) {
-  int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v <= n) out[v] = a[v] + b[v];
+// Row offsets without counters: the canonical edges are sorted by their
+// smaller endpoint (eu) and, in a second copy, by their larger one (lo_v), so
+// uppre[x] / lowpre[x] = edges whose smaller / larger endpoint is below x
+// are lower bounds in those arrays; row x of the symmetric CSR starts at
+// uppre[x] + lowpre[x] and holds its lower neighbours, then its upper ones.
+__global__ void k_row_bounds(const int32_t* __restrict__ eu, const int32_t* __restrict__ lo_v, int64_t m, int32_t n,
+                             int64_t* __restrict__ uppre, int64_t* __restrict__ lowpre,
+                             int64_t* __restrict__ row_ptr) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x > n) return;
+  const int64_t a = lower_bound_i32<int64_t>(eu, 0, m, (int)x);
+  const int64_t b = lower_bound_i32<int64_t>(lo_v, 0, m, (int)x);
+  uppre[x] = a;
+  lowpre[x] = b;
+  row_ptr[x] = a + b;
 }
 
-__device__ __forceinline__ int64_t deg_of(const int64_t* __restrict__ rp, int32_t v) { return rp[v + 1] - rp[v]; }
-
+// upper entry of canonical edge e = (u, v): the tail of u's row, after its
+// lower entries (row_ptr[u+1] = uppre[u+1] + lowpre[u+1])
 __global__ void k_sym_upper(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
-                            const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ lowcnt,
-                            const int64_t* __restrict__ uppre, int32_t* __restrict__ col,
-                            int32_t* __restrict__ seid, int32_t* __restrict__ kf) {
+                            const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ lowpre,
+                            int32_t* __restrict__ col, int32_t* __restrict__ seid, int32_t* __restrict__ kf) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= m) return;
   int32_t u = eu[e], v = ev[e];
-  int64_t pos = row_ptr[u] + lowcnt[u] + (e - uppre[u]);
+  int64_t pos = lowpre[u + 1] + e;
   col[pos] = v;
   seid[pos] = (int32_t)e;
   kf[pos] = vertex_before(deg_of(row_ptr, u), u, deg_of(row_ptr, v), v) ? 1 : 0;
@@ -95,8 +103,10 @@ __global__ void k_copy_ev(const int32_t* __restrict__ ev, int64_t m, uint32_t* _
   tval[e] = (int32_t)e;
 }
 
+// lower entry of edge tval[t] = (u, v) with v = tkey[t]: the head of v's row,
+// in canonical order (row_ptr[v] = uppre[v] + lowpre[v])
 __global__ void k_sym_lower(const uint32_t* __restrict__ tkey, const int32_t* __restrict__ tval, int64_t m,
-                            const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ lowpre,
+                            const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ uppre,
                             const int32_t* __restrict__ eu, int32_t* __restrict__ col,
                             int32_t* __restrict__ seid, int32_t* __restrict__ kf) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -104,7 +114,7 @@ __global__ void k_sym_lower(const uint32_t* __restrict__ tkey, const int32_t* __
   int32_t e = tval[t];
   int32_t v = (int32_t)tkey[t];
   int32_t u = eu[e];
-  int64_t pos = row_ptr[v] + (t - lowpre[v]);
+  int64_t pos = uppre[v] + t;
   col[pos] = u;
   seid[pos] = e;
   kf[pos] = vertex_before(deg_of(row_ptr, v), v, deg_of(row_ptr, u), u) ? 1 : 0;
@@ -206,10 +216,12 @@ __global__ void k_csr_upper(const int32_t* __restrict__ col, const int32_t* __re
   int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= m2) return;
   const int32_t v = rowid[j], w = col[j];
-  colcopy[j] = w;
+  if (colcopy) {
+    colcopy[j] = w;
+    if (w > v) seid[j] = (int32_t)upos[j];
+  }
   if (w > v) {
     const int64_t e = upos[j];
-    seid[j] = (int32_t)e;
     eu[e] = v;
     ev[e] = w;
   }
@@ -228,6 +240,22 @@ __global__ void k_csr_lower(const int64_t* __restrict__ row_ptr, const int32_t* 
     else seid[j] = (int32_t)upos[p];
   }
   kf[j] = vertex_before(deg_of(row_ptr, v), v, deg_of(row_ptr, w), w) ? 1 : 0;
+}
+
+// Symmetry of a CSR input built through the relabelled path: the graph was
+// built from the upper entries alone (m of them, no repeats), so the input is
+// symmetric iff every lower entry (v, w), w < v, is an edge of that graph --
+// looked up in the row table of v's new id.
+__global__ void k_csr_sym_check(const int32_t* __restrict__ col_in, const int32_t* __restrict__ rowid, int64_t m2,
+                                const int32_t* __restrict__ rank, const int2* __restrict__ rtab,
+                                const int64_t* __restrict__ rtoff, int* err) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m2) return;
+  const int32_t v = rowid[j], w = col_in[j];
+  if (w >= v) return;
+  const int32_t x = rank[v];
+  const int64_t off = rtoff[x], slots = rtoff[x + 1] - off;
+  if (slots == 0 || row_lookup(rtab, off, row_table_lg(slots), rank[w]) < 0) report(err, kErrAsym);
 }
 
 __global__ void k_check_total(const int64_t* __restrict__ upos, int64_t m2, int64_t m, int* err) {
@@ -326,7 +354,6 @@ struct Layout {
   // temporaries
   uint64_t *key, *key_alt;
   int32_t *val, *val_alt;
-  int32_t *upcnt, *lowcnt;
   int64_t *uppre, *lowpre;
   int32_t *rowid, *kf;
   int64_t *opos;
@@ -366,8 +393,6 @@ void carve(const truss_graph* g, bool relabel, Arena& a, Layout& L) {
     L.key_alt = a.take<uint64_t>(m + 1);
     L.val = a.take<int32_t>(m + 1);
     L.val_alt = a.take<int32_t>(m + 1);
-    L.upcnt = a.take<int32_t>(n + 1);
-    L.lowcnt = a.take<int32_t>(n + 1);
     L.uppre = a.take<int64_t>(n + 1);
     L.lowpre = a.take<int64_t>(n + 1);
     L.rtmp = a.take<int32_t>(radix_tmp_elems(m + 1));
@@ -376,7 +401,6 @@ void carve(const truss_graph* g, bool relabel, Arena& a, Layout& L) {
     L.rowid = a.take<int32_t>(m2 + 1);
     L.key = L.key_alt = nullptr;
     L.val = L.val_alt = nullptr;
-    L.upcnt = L.lowcnt = nullptr;
     L.uppre = L.lowpre = nullptr;
     L.rtmp = nullptr;
   }
@@ -406,23 +430,20 @@ void degree_ranks(const int64_t* row_ptr, const int32_t* deg, int32_t n, int vb,
 // L.key / L.val (val: the caller's index of each edge)
 int rows_from_keys(int32_t n, int64_t m, int vb, Layout& L, int* d_err, hipStream_t s) {
   radix_sort_u64(L.key, L.val, L.key_alt, L.val_alt, m, 2 * vb, L.rtmp, s);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.upcnt, (int64_t)n + 1, 0);
-  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.lowcnt, (int64_t)n + 1, 0);
   hipLaunchKernelGGL(k_edges_from_keys, dim3(grid_for(m)), dim3(kT), 0, s, L.key, L.val, m, vb, L.eu, L.ev, L.perm,
-                     L.upcnt, L.lowcnt, d_err);
+                     d_err);
   const int rc = read_err(d_err, s);
   if (rc) return rc;
-  scan_exclusive_i32_to_i64(L.upcnt, L.uppre, n, L.stmp, s);
-  scan_exclusive_i32_to_i64(L.lowcnt, L.lowpre, n, L.stmp, s);
-  hipLaunchKernelGGL(k_rowptr_sum, dim3(grid_for(n + 1)), dim3(kT), 0, s, L.uppre, L.lowpre, n, L.row_ptr);
-  hipLaunchKernelGGL(k_sym_upper, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.row_ptr, L.lowcnt, L.uppre,
-                     L.col, L.seid, L.kf);
-  // lower halves of the rows: stable sort of the canonical order by the larger endpoint
+  // the canonical order, stably sorted by the larger endpoint (lower halves of the rows)
   uint32_t* tkey = reinterpret_cast<uint32_t*>(L.key);
   uint32_t* tkey_alt = reinterpret_cast<uint32_t*>(L.key_alt);
   hipLaunchKernelGGL(k_copy_ev, dim3(grid_for(m)), dim3(kT), 0, s, L.ev, m, tkey, L.val);
   radix_sort_u32(tkey, L.val, tkey_alt, L.val_alt, m, vb, L.rtmp, s);
-  hipLaunchKernelGGL(k_sym_lower, dim3(grid_for(m)), dim3(kT), 0, s, tkey, L.val, m, L.row_ptr, L.lowpre, L.eu,
+  hipLaunchKernelGGL(k_row_bounds, dim3(grid_for((int64_t)n + 1)), dim3(kT), 0, s, L.eu,
+                     reinterpret_cast<const int32_t*>(tkey), m, n, L.uppre, L.lowpre, L.row_ptr);
+  hipLaunchKernelGGL(k_sym_upper, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.row_ptr, L.lowpre, L.col,
+                     L.seid, L.kf);
+  hipLaunchKernelGGL(k_sym_lower, dim3(grid_for(m)), dim3(kT), 0, s, tkey, L.val, m, L.row_ptr, L.uppre, L.eu,
                      L.col, L.seid, L.kf);
   return TRUSS_OK;
 }
@@ -478,15 +499,13 @@ int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStr
     hipLaunchKernelGGL(k_check_total, dim3(1), dim3(1), 0, s, upos, m2, m, d_err);
     rc = read_err(d_err, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_csr_upper, dim3(grid_for(m2)), dim3(kT), 0, s, g->col, L.rowid, upos, m2, L.col, L.seid,
-                       L.eu, L.ev);
-    hipLaunchKernelGGL(k_csr_lower, dim3(grid_for(m2)), dim3(kT), 0, s, g->row_ptr, g->col, L.rowid, upos, m2,
-                       L.seid, L.kf, d_err);
-    rc = read_err(d_err, s);
-    if (rc) return rc;
+    // canonical edges; the entries themselves are kept only when the input rows are used as they are
+    hipLaunchKernelGGL(k_csr_upper, dim3(grid_for(m2)), dim3(kT), 0, s, g->col, L.rowid, upos, m2,
+                       relabel ? nullptr : L.col, L.seid, L.eu, L.ev);
     if (relabel) {
-      // the validated canonical edges, renamed, go through the edge-list build;
-      // perm then maps each edge to its canonical CSR position
+      // the canonical edges (the upper entries), renamed, go through the
+      // edge-list build; perm then maps each edge to its canonical CSR
+      // position.  Symmetry is checked on the row tables at the end.
       degree_ranks(g->row_ptr, nullptr, n, vb, L, s);
       hipLaunchKernelGGL(k_canon_relabel, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, vb, L.rank, L.key,
                          L.val);
@@ -494,6 +513,9 @@ int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStr
       dg.row_ptr = L.row_ptr;
       dg.perm = L.perm;
     } else {
+      hipLaunchKernelGGL(k_csr_lower, dim3(grid_for(m2)), dim3(kT), 0, s, g->row_ptr, g->col, L.rowid, upos, m2,
+                         L.seid, L.kf, d_err);
+      if ((rc = read_err(d_err, s))) return rc;
       dg.row_ptr = g->row_ptr;
       dg.perm = nullptr;
     }
@@ -521,6 +543,11 @@ int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStr
   TRUSS_HIP(hipGetLastError());
   dg.rtab = L.rtab;
   dg.rtoff = L.rtoff;
+  if (relabel && g->fmt == TRUSS_FMT_CSR && m2 > 0) {
+    hipLaunchKernelGGL(k_csr_sym_check, dim3(grid_for(m2)), dim3(kT), 0, s, g->col, L.rowid, m2, L.rank, L.rtab,
+                       L.rtoff, d_err);
+    return read_err(d_err, s);
+  }
   return TRUSS_OK;
 }
 

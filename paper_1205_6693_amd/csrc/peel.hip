@@ -965,10 +965,25 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
   if (tid == 0 && my_work) atomicAdd(&c->w_work, my_work);
 }
 
+// One bit per edge, set when the edge is removed: the liveness test of the
+// row compaction reads this bitmap (m/8 bytes, cache-resident) instead of
+// one scattered support/stamp pair per row entry.
+__global__ void __launch_bounds__(256) k_dead_bits(const int2* __restrict__ sr, int64_t m,
+                                                   unsigned long long* __restrict__ dead) {
+  const int lane = lane_id();
+  const int64_t gw = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t base = gw * kWave; base < m; base += nw * kWave) {
+    const int64_t e = base + lane;
+    const unsigned long long bits = ballot(e < m && sr[e].y != 0);
+    if (lane == 0) dead[base / kWave] = bits;
+  }
+}
+
 // Stable in-place compaction of every row to its live entries (a wavefront a row).
 __global__ void __launch_bounds__(256) k_compact(const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
                                                  int32_t* __restrict__ seid, int32_t* __restrict__ rlen, int32_t n,
-                                                 const int2* __restrict__ sr, PeelCtl* c) {
+                                                 const unsigned long long* __restrict__ dead, PeelCtl* c) {
   const int lane = lane_id();
   const int64_t gw = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -987,7 +1002,7 @@ __global__ void __launch_bounds__(256) k_compact(const int64_t* __restrict__ row
       if (i < len) {
         x = col[rb + i];
         ed = seid[rb + i];
-        keep = sr[ed].y == 0;
+        keep = ((dead[ed >> 6] >> (ed & 63)) & 1ULL) == 0;
       }
       const uint64_t km = ballot(keep);
       if (keep) {
@@ -1062,6 +1077,7 @@ struct PeelLayout {
   unsigned long long* pslot;
   int32_t *rec_e, *rec_b, *rec_pre, *rec_tot;
   int64_t* rec_base;
+  unsigned long long* dead;  // removed-edge bitmap for the row compaction
   int pcap;
 };
 
@@ -1078,6 +1094,7 @@ void carve(const DevGraph& dg, Arena& a, PeelLayout& L) {
   L.rec_pre = a.take<int32_t>(m + kT);
   L.rec_base = a.take<int64_t>(m + kT);
   L.rec_tot = a.take<int32_t>(m / kMinChunk + 2);
+  L.dead = a.take<unsigned long long>(m / kWave + 2);
 }
 
 int g_peel_blocks = 0;
@@ -1163,7 +1180,9 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
       if (hipEventElapsedTime(&t, ev0, ev1) == hipSuccess) kernel_ms += t;
     }
     if (h.abort || h.err || h.phase != PH_COMPACT) break;
-    hipLaunchKernelGGL(k_compact, dim3(2048), dim3(256), 0, s, dg.row_ptr, dg.col, dg.seid, L.rlen, dg.n, sr, L.ctl);
+    hipLaunchKernelGGL(k_dead_bits, dim3(4096), dim3(256), 0, s, sr, dg.m, L.dead);
+    hipLaunchKernelGGL(k_compact, dim3(2048), dim3(256), 0, s, dg.row_ptr, dg.col, dg.seid, L.rlen, dg.n, L.dead,
+                       L.ctl);
   }
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
