@@ -96,6 +96,15 @@ typedef struct truss_graph {
 #define TRUSS_PROBE_HASH 1    /* hash table over the edges, as Section 3.2 keeps E_G */
 #define TRUSS_PROBE_BSEARCH 2 /* binary search of the other endpoint's sorted row  */
 
+/* Shape of the persistent peeling kernel (a tuning choice; results are the
+ * same): one 1024-thread workgroup per compute unit with four walk entries in
+ * flight per thread, or two workgroups per compute unit with two entries per
+ * thread (more wavefronts to hide memory latency).  AUTO takes the wide shape
+ * for graphs of at least 2^27 edges, where it measured faster. */
+#define TRUSS_SHAPE_AUTO 0
+#define TRUSS_SHAPE_NARROW 1
+#define TRUSS_SHAPE_WIDE 2
+
 /* Scheduler used for the AUTO decisions: the intersection strategy of each
  * support bin (vertices grouped by out-degree) and, for each peeling level, the
  * frontier mode and the membership probe.  Every choice computes the same
@@ -123,7 +132,9 @@ typedef struct truss_options {
                                total) is rejected like a malformed one (the
                                heuristic runs, sched_fallback = 1); 0: the
                                caller vouches for the length              */
-  int32_t reserved[3];
+  int32_t peel_shape;       /* TRUSS_SHAPE_* (ignored when grid_blocks > 0: the
+                               narrow shape runs with that grid)             */
+  int32_t reserved[2];
 } truss_options;
 
 /* Filled when a stats pointer is passed (host). */

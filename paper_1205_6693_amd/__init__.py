@@ -42,6 +42,7 @@ FMT_EDGES, FMT_CSR = 0, 1
 SUP_AUTO, SUP_HASH, SUP_BSEARCH, SUP_MERGE = 0, 1, 2, 3
 PEEL_AUTO, PEEL_SPARSE, PEEL_DENSE = 0, 1, 2
 PROBE_AUTO, PROBE_HASH, PROBE_BSEARCH = 0, 1, 2
+SHAPE_AUTO, SHAPE_NARROW, SHAPE_WIDE = 0, 1, 2
 SCHED_PLAIN, SCHED_HEURISTIC, SCHED_LEARNED = 0, 1, 2
 SCHED_PEEL_F, SCHED_PEEL_A, SCHED_SUP_BINS, SCHED_SUP_F, SCHED_SUP_A = 8, 4, 4, 6, 3
 
@@ -64,7 +65,8 @@ class Options(ctypes.Structure):
                 ("model", ctypes.c_void_p), ("max_subrounds", ctypes.c_int64),
                 ("grid_blocks", ctypes.c_int32), ("peel_probe", ctypes.c_int32),
                 ("batch_block", ctypes.c_int32), ("batch_ilp", ctypes.c_int32),
-                ("model_floats", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("model_floats", ctypes.c_int32), ("peel_shape", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -306,11 +308,11 @@ class Graph:
 
 def make_options(support_strategy=SUP_AUTO, peel_mode=PEEL_AUTO, scheduler=SCHED_HEURISTIC,
                  model=None, max_subrounds=0, grid_blocks=0, peel_probe=PROBE_AUTO, batch_block=0,
-                 batch_ilp=0):
+                 batch_ilp=0, peel_shape=SHAPE_AUTO):
     o = Options()
     load_library().truss_default_options(ctypes.byref(o))
     o.support_strategy, o.peel_mode, o.scheduler = support_strategy, peel_mode, scheduler
-    o.peel_probe = peel_probe
+    o.peel_probe, o.peel_shape = peel_probe, peel_shape
     o.batch_block, o.batch_ilp = batch_block, batch_ilp
     if model is not None:
         _dev(model, "model", _torch().float32, 4)

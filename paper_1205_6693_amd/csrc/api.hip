@@ -88,6 +88,7 @@ int validate_options(const truss_options* o) {
       o->peel_mode < TRUSS_PEEL_AUTO || o->peel_mode > TRUSS_PEEL_DENSE ||
       o->scheduler < TRUSS_SCHED_PLAIN || o->scheduler > TRUSS_SCHED_LEARNED ||
       o->peel_probe < TRUSS_PROBE_AUTO || o->peel_probe > TRUSS_PROBE_BSEARCH ||
+      o->peel_shape < TRUSS_SHAPE_AUTO || o->peel_shape > TRUSS_SHAPE_WIDE ||
       !(o->batch_block == 0 || o->batch_block == 256 || o->batch_block == 512 || o->batch_block == 1024) ||
       !(o->batch_ilp == 0 || o->batch_ilp == 1 || o->batch_ilp == 2 || o->batch_ilp == 4)) {
     set_last_error("option out of range");
@@ -157,6 +158,7 @@ void resolve(const truss_options* in, SupPlan* sp, PeelPlan* pp, int* fallback, 
   }
   pp->max_subrounds = o.max_subrounds;
   pp->grid_blocks = o.grid_blocks;
+  pp->shape = o.peel_shape;
 }
 
 struct Plan {

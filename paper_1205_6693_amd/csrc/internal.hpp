@@ -89,6 +89,7 @@ struct PeelPlan {
   const float* model = nullptr;       // (device) peeling model part when learned
   long long max_subrounds = 0;
   int grid_blocks = 0;
+  int shape = TRUSS_SHAPE_AUTO;  // kernel shape (TRUSS_SHAPE_*)
   int first_level = 2;  // the first level peeled takes every live edge with sup <= first_level - 2
   int stop_level = 0;   // > 0: stop once the next level would exceed it (later edges keep no truss number)
   bool timed = true;    // time the kernel's launches with HIP events

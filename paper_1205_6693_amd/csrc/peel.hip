@@ -448,19 +448,18 @@ __device__ bool phase_barrier(PeelCtl* c, const PeelArgs& P) {
 
 __device__ __forceinline__ bool removed_at(int rnd, int r) { return rnd != 0 && rnd < r; }
 
-// kNI adjacency entries of walks, one step at a time for all of them so that
+// NI adjacency entries of walks, one step at a time for all of them so that
 // their memory accesses are in flight together.  Entry q is position j[q] of
 // the row walked for frontier edge e[q] = (a, b[q]), valid if ok[q].  Outputs
 // the (up to two) edges per entry whose support crossed k-1 -> k-2 and must be
 // enqueued.
-constexpr int kNI = 4;
-
-__device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t (&e)[kNI], const int32_t (&b)[kNI],
-                                                const int64_t (&j)[kNI], bool (&ok)[kNI], int r, int l, int k,
-                                                bool sparse, int probe, int32_t (&f1)[kNI], int32_t (&f2)[kNI]) {
-  int32_t w[kNI], e1[kNI], e2[kNI], s1[kNI], s2[kNI];
+template <int NI>
+__device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t (&e)[NI], const int32_t (&b)[NI],
+                                                const int64_t (&j)[NI], bool (&ok)[NI], int r, int l, int k,
+                                                bool sparse, int probe, int32_t (&f1)[NI], int32_t (&f2)[NI]) {
+  int32_t w[NI], e1[NI], e2[NI], s1[NI], s2[NI];
 #pragma unroll
-  for (int q = 0; q < kNI; ++q) {
+  for (int q = 0; q < NI; ++q) {
     f1[q] = -1;
     f2[q] = -1;
     w[q] = -1;
@@ -475,21 +474,21 @@ __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t
   }
   // the first other edge (a, w) must not be removed
 #pragma unroll
-  for (int q = 0; q < kNI; ++q) {
+  for (int q = 0; q < NI; ++q) {
     ok[q] = ok[q] && w[q] != b[q];
     if (ok[q]) s1[q] = ldc_stamp(&P.sr[e1[q]]);
   }
 #pragma unroll
-  for (int q = 0; q < kNI; ++q) ok[q] = ok[q] && !removed_at(s1[q], r);
+  for (int q = 0; q < NI; ++q) ok[q] = ok[q] && !removed_at(s1[q], r);
   // the second other edge (b, w): b's row hash table, or a binary search of
   // b's sorted row (the entries of one walk look up the same row, so they
   // touch the same few cached lines either way)
   if (probe == 0) {
-    const int2* tb[kNI];
-    uint32_t h[kNI], mask[kNI];
-    int2 sl[kNI];
+    const int2* tb[NI];
+    uint32_t h[NI], mask[NI];
+    int2 sl[NI];
 #pragma unroll
-    for (int q = 0; q < kNI; ++q) {  // the first slots of all lookups in flight together
+    for (int q = 0; q < NI; ++q) {  // the first slots of all lookups in flight together
       tb[q] = P.rtab;
       h[q] = 0;
       mask[q] = 0;
@@ -504,7 +503,7 @@ __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t
       }
     }
 #pragma unroll
-    for (int q = 0; q < kNI; ++q) {
+    for (int q = 0; q < NI; ++q) {
       if (!ok[q]) continue;
       while (sl[q].x != w[q] && sl[q].x >= 0) {
         h[q] = (h[q] + 1) & mask[q];
@@ -515,7 +514,7 @@ __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < kNI; ++q) {
+    for (int q = 0; q < NI; ++q) {
       if (!ok[q]) continue;
       const int64_t rb = P.row_ptr[b[q]];
       const int64_t re = rb + P.rlen[b[q]];
@@ -525,14 +524,14 @@ __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t
     }
   }
 #pragma unroll
-  for (int q = 0; q < kNI; ++q)
+  for (int q = 0; q < NI; ++q)
     if (ok[q]) s2[q] = ldc_stamp(&P.sr[e2[q]]);
   // the triangle is destroyed now unless an edge is removed, and it belongs
   // to its frontier edge of smallest id; each other edge not in F_r loses one
-  bool d1[kNI], d2[kNI];
-  int old1[kNI], old2[kNI];
+  bool d1[NI], d2[NI];
+  int old1[NI], old2[NI];
 #pragma unroll
-  for (int q = 0; q < kNI; ++q) {
+  for (int q = 0; q < NI; ++q) {
     const bool live = ok[q] && !removed_at(s2[q], r) && !(s1[q] == r && e1[q] < e[q]) &&
                       !(s2[q] == r && e2[q] < e[q]);
     d1[q] = live && s1[q] != r;
@@ -544,7 +543,7 @@ __device__ __forceinline__ void process_entries(const PeelArgs& P, const int32_t
   }
   if (!sparse) return;
 #pragma unroll
-  for (int q = 0; q < kNI; ++q) {
+  for (int q = 0; q < NI; ++q) {
     if (d1[q] && old1[q] == l + 1) {
       stc_stamp(&P.sr[e1[q]], r + 1);
       P.truss[e1[q]] = k;
@@ -679,7 +678,8 @@ __device__ __forceinline__ int block_inclusive_sum(int x, int* tmp, int* total) 
   return base + inc;
 }
 
-__global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
+template <int NI>
+__device__ __forceinline__ void peel_body(const PeelArgs& P) {
   __shared__ int s_pre[kT + 1];
   __shared__ int s_e[kT];
   __shared__ int s_b[kT];
@@ -787,12 +787,12 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
       unsigned long long* slots = P.pslot;
       // walk items [lo, hi) of the chunk held in the workgroup's LDS tables
       auto walk = [&](int lo, int hi) {
-        for (int t0 = lo; t0 < hi; t0 += kNI * kT) {
-          int32_t e[kNI], b[kNI], f1[kNI], f2[kNI];
-          int64_t j[kNI];
-          bool ok[kNI];
+        for (int t0 = lo; t0 < hi; t0 += NI * kT) {
+          int32_t e[NI], b[NI], f1[NI], f2[NI];
+          int64_t j[NI];
+          bool ok[NI];
 #pragma unroll
-          for (int q = 0; q < kNI; ++q) {
+          for (int q = 0; q < NI; ++q) {
             const int t = t0 + q * kT + tid;
             ok[q] = t < hi;
             e[q] = 0;
@@ -809,9 +809,9 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
               j[q] = s_base[x] + (t - s_pre[x]);
             }
           }
-          process_entries(P, e, b, j, ok, r, l, k, sparse, probe, f1, f2);
+          process_entries<NI>(P, e, b, j, ok, r, l, k, sparse, probe, f1, f2);
 #pragma unroll
-          for (int q = 0; q < kNI; ++q) wq_push(wq, f1[q], f2[q]);
+          for (int q = 0; q < NI; ++q) wq_push(wq, f1[q], f2[q]);
         }
         if (tid == 0) my_work += (unsigned long long)(hi - lo);
       };
@@ -965,6 +965,16 @@ __global__ void __launch_bounds__(kT) k_peel(PeelArgs P) {
   if (tid == 0 && my_work) atomicAdd(&c->w_work, my_work);
 }
 
+// The persistent peeling kernel in two shapes over the same state machine:
+// one 1024-thread workgroup per compute unit with four walk entries in flight
+// per thread, or two workgroups per compute unit (registers capped for eight
+// wavefronts per SIMD) with two entries per thread, which hides more latency
+// when walks are long.  All state lives in global memory between launches.
+__global__ void __launch_bounds__(kT) k_peel(PeelArgs P) { peel_body<4>(P); }
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) k_peel_wide(PeelArgs P) {
+  peel_body<2>(P);
+}
+
 // One bit per edge, set when the edge is removed: the liveness test of the
 // row compaction reads this bitmap (m/8 bytes, cache-resident) instead of
 // one scattered support/stamp pair per row entry.
@@ -1097,7 +1107,14 @@ void carve(const DevGraph& dg, Arena& a, PeelLayout& L) {
   L.dead = a.take<unsigned long long>(m / kWave + 2);
 }
 
-int g_peel_blocks = 0;
+int g_peel_blocks = 0;       // grid of k_peel: one workgroup per compute unit
+int g_peel_wide_blocks = -1;  // grid of k_peel_wide (two per compute unit), 0 if it does not fit
+
+// TRUSS_SHAPE_AUTO takes the wide shape from this many edges on: there its
+// extra wavefronts hide the latency of long walks in every launch, while on
+// smaller graphs the shorter rounds favour the narrow shape (fewer workgroups
+// at each barrier, more entries in flight per thread).
+constexpr long long kWideMinEdges = 1LL << 27;
 
 }  // namespace
 
@@ -1129,10 +1146,16 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
       set_last_error("peeling kernel does not fit on a compute unit");
       return TRUSS_E_DEVICE;
     }
-    g_peel_blocks = cus;  // one workgroup per compute unit
+    g_peel_blocks = cus;
+    int occw = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occw, (const void*)k_peel_wide, kT, 0) != hipSuccess) occw = 0;
+    g_peel_wide_blocks = occw >= 2 ? 2 * cus : 0;
   }
   int blocks = g_peel_blocks;
   if (plan.grid_blocks > 0 && plan.grid_blocks < blocks) blocks = plan.grid_blocks;
+  // a caller-fixed grid keeps the narrow shape
+  const bool wide = plan.grid_blocks <= 0 && g_peel_wide_blocks > 0 &&
+                    (plan.shape == TRUSS_SHAPE_WIDE || (plan.shape == TRUSS_SHAPE_AUTO && dg.m >= kWideMinEdges));
   PeelArgs P;
   P.n = dg.n;
   P.m = dg.m;
@@ -1169,7 +1192,10 @@ int peel(const DevGraph& dg, const PeelPlan& plan, int2* sr, int32_t* truss_cano
   double kernel_ms = 0.0;
   for (;;) {
     if (timed) (void)hipEventRecord(ev0, s);
-    hipLaunchKernelGGL(k_peel, dim3(blocks), dim3(kT), 0, s, P);
+    if (wide)
+      hipLaunchKernelGGL(k_peel_wide, dim3(g_peel_wide_blocks), dim3(kT), 0, s, P);
+    else
+      hipLaunchKernelGGL(k_peel, dim3(blocks), dim3(kT), 0, s, P);
     TRUSS_HIP(hipGetLastError());
     if (timed) (void)hipEventRecord(ev1, s);
     ++launches;

@@ -69,7 +69,9 @@ __global__ void k_sup_zero(int32_t* __restrict__ supo, int64_t m, SupCtl* ctl) {
 
 // Bins the vertices by d+ = |N+(a)| and sums d+ and d+^2 per bin; counts are
 // gathered per wavefront, then per workgroup, so each bin counter sees one
-// atomic per workgroup.
+// atomic per workgroup.  A bin's list comes out roughly in id order; with ids
+// ranked by degree, the hash kernels take it backwards, so the vertices with
+// the most pairs start first and the short ones fill the tail.
 constexpr int kBinT = 1024;
 __global__ void __launch_bounds__(kBinT) k_sup_bin(const int64_t* __restrict__ orow, int32_t n,
                                                    int32_t* __restrict__ vlist, SupCtl* ctl) {
@@ -444,7 +446,7 @@ __global__ void __launch_bounds__(kT) k_sup_hash_wave(const int64_t* __restrict_
     if (first >= count) break;
     const int last = first + kFetch0 < count ? first + kFetch0 : count;
     for (int idx = first; idx < last; ++idx) {
-      const int32_t a = vlist[idx];
+      const int32_t a = vlist[count - 1 - idx];  // the bin's list backwards: see k_sup_bin
       const int64_t base = orow[a];
       const int d = (int)(orow[a + 1] - base);
       if (lane == 0) s_nrev[w] = 0;
@@ -494,7 +496,7 @@ __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(8, 8))
     const int idx = s_idx;
     __syncthreads();
     if (idx >= count) break;
-    const int32_t a = vlist[(int64_t)bin * n + idx];
+    const int32_t a = vlist[(int64_t)bin * n + (count - 1 - idx)];
     const int64_t base = orow[a];
     const int d = (int)(orow[a + 1] - base);
     const int nrows = stage_rows<LOGTAB, NTH, MAXD>(orow, ocol, base, d, s_tab, s_nb, s_pre, s_offj, s_wi, s_cnt,

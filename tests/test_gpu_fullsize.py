@@ -28,7 +28,8 @@ WORKLOADS = {
 # scheduler 0 = plain (merge support, dense frontier, bsearch probes),
 # 1 = fixed heuristic (the default), 2 = learned with the committed model (the
 # form the benchmark times, in its launch configuration)
-SCHEDULERS = [dict(), dict(scheduler=0), "learned"]
+# "other shape": the peeling kernel shape the default does not pick for this size
+SCHEDULERS = [dict(), dict(scheduler=0), "learned", "other shape"]
 
 
 def _options(opt):
@@ -54,7 +55,10 @@ def test_fullsize_digest(name):
     assert golden_io.int32_digest(sup) == rec["support_sha256"]
     for opt in SCHEDULERS:
         say(f"  options {opt}")
-        phi, st = gpu_truss(g, **_options(opt))
+        if opt == "other shape":
+            phi, st = gpu_truss(g, peel_shape=2 if g.m < (1 << 27) else 1)
+        else:
+            phi, st = gpu_truss(g, **_options(opt))
         if opt == "learned":
             assert st["sched_fallback"] == 0
         hist = np.bincount(phi, minlength=rec["kmax"] + 1)

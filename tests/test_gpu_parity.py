@@ -19,10 +19,10 @@ pytestmark = pytest.mark.gpu
 
 # option sets: support strategy (1 hash, 2 bsearch, 3 merge), frontier mode
 # (1 sparse, 2 dense), membership probe while peeling (1 hash table, 2 bsearch)
-STRATS = [dict(support_strategy=1, peel_mode=1, peel_probe=1),
-          dict(support_strategy=2, peel_mode=2, peel_probe=2),
-          dict(support_strategy=3, peel_mode=1, peel_probe=2),
-          dict(support_strategy=1, peel_mode=2, peel_probe=1),
+STRATS = [dict(support_strategy=1, peel_mode=1, peel_probe=1, peel_shape=1),
+          dict(support_strategy=2, peel_mode=2, peel_probe=2, peel_shape=2),
+          dict(support_strategy=3, peel_mode=1, peel_probe=2, peel_shape=1),
+          dict(support_strategy=1, peel_mode=2, peel_probe=1, peel_shape=2),
           dict(support_strategy=2, peel_mode=1, peel_probe=2)]
 
 

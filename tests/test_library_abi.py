@@ -86,6 +86,13 @@ def test_argument_errors_before_device_work(T):
     o.version = T.TRUSS_VERSION
     o.peel_mode = 9
     assert lib.truss_workspace_size(ctypes.byref(_graph(T, 5, 5)), ctypes.byref(o), ctypes.byref(b)) == T.E_INVAL
+    o.peel_mode = 0
+    for shape in (T.SHAPE_AUTO, T.SHAPE_NARROW, T.SHAPE_WIDE):
+        o.peel_shape = shape
+        assert lib.truss_workspace_size(ctypes.byref(_graph(T, 5, 5)), ctypes.byref(o), ctypes.byref(b)) == T.OK
+    o.peel_shape = 3
+    assert lib.truss_workspace_size(ctypes.byref(_graph(T, 5, 5)), ctypes.byref(o), ctypes.byref(b)) == T.E_INVAL
+    o.peel_shape = 0
     # decompose with NULL output or too small workspace fails on the host
     g = _graph(T, 5, 5)
     assert lib.truss_decompose(ctypes.byref(g), None, None, None, None, 0, None) == T.E_INVAL
