@@ -67,6 +67,7 @@ constexpr int kHistBins = 6;
 constexpr long long kCompactNum = 8, kCompactDen = 10;  // row compaction threshold
 constexpr int kStageA = 8192;  // LDS staging of live-list appends (entries)
 constexpr int kStageQ = 2048;  // LDS staging of frontier-queue appends
+static_assert(4 * kT <= kStageA && 2 * kT <= kStageQ, "sweep staging capacity");
 constexpr int kMinChunk = 64;  // smallest frontier chunk
 
 // Frontier edges per chunk in a round with qn frontier edges: the frontier is
@@ -634,6 +635,35 @@ __device__ __forceinline__ void staged_append(StagedList& L, bool want, int32_t 
   __syncthreads();
 }
 
+// The same for U candidate entries per thread (vals[u] kept where want[u]);
+// a thread's kept entries stay in order and follow the previous thread's.
+// U * kT must not exceed the list's LDS capacity.
+template <int U>
+__device__ __forceinline__ void staged_append_n(StagedList& L, const bool (&want)[U], const int32_t (&vals)[U],
+                                                int* tmp) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  int cnt = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) cnt += want[u] ? 1 : 0;
+  const int incl = wave_inclusive_sum(cnt);
+  if (lane == kWave - 1) tmp[w] = incl;
+  __syncthreads();
+  int wbase = 0, tot = 0;
+  for (int q = 0; q < kWaves; ++q) {
+    const int x = tmp[q];
+    if (q < w) wbase += x;
+    tot += x;
+  }
+  if (*L.fill + tot > L.cap) staged_flush(L);
+  int pos = *L.fill + wbase + incl - cnt;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (want[u]) L.buf[pos++] = vals[u];
+  __syncthreads();
+  if (threadIdx.x == 0) *L.fill += tot;
+  __syncthreads();
+}
+
 // minimum over the workgroup into *dst (one atomic per workgroup); tmp: kWaves ints
 __device__ __forceinline__ void block_min_to(int x, int* tmp, int* dst) {
   x = wave_min(x);
@@ -678,8 +708,11 @@ __device__ __forceinline__ int block_inclusive_sum(int x, int* tmp, int* total) 
   return base + inc;
 }
 
-template <int NI>
+// NI: walk entries in flight per thread; SU (2 or 4): live-list entries per
+// thread and step of the level sweep
+template <int NI, int SU>
 __device__ __forceinline__ void peel_body(const PeelArgs& P) {
+  static_assert(SU == 2 || SU == 4, "sweep step");
   __shared__ int s_pre[kT + 1];
   __shared__ int s_e[kT];
   __shared__ int s_b[kT];
@@ -723,27 +756,45 @@ __device__ __forceinline__ void peel_body(const PeelArgs& P) {
       const int kt = k + 1, stamp = r + 1;
       int mins = kIntMax;
       unsigned long long wsum = 0;
-      for (int64_t base = (int64_t)blockIdx.x * kT; base < cnt; base += (int64_t)gridDim.x * kT) {
-        const int64_t i = base + tid;
-        bool live = false, take = false;
-        int32_t e = 0;
-        if (i < cnt) {
-          e = first ? (int32_t)i : ldc(&A[i]);
-          const int2 sv = ldc2(&P.sr[e]);
-          live = sv.y == 0;
-          if (live) {
-            mins = sv.x < mins ? sv.x : mins;
-            take = sv.x <= kt - 2;
-            if (take) {
-              stc_stamp(&P.sr[e], stamp);
-              P.truss[e] = kt;
-              const int du = P.rlen[P.eu[e]], dv = P.rlen[P.ev[e]];
+      // SU consecutive list entries a thread, their loads in flight together
+      for (int64_t base = (int64_t)blockIdx.x * kT * SU; base < cnt; base += (int64_t)gridDim.x * kT * SU) {
+        const int64_t i0 = base + (int64_t)tid * SU;
+        int32_t e[SU];
+        int2 sv[SU];
+        bool live[SU], take[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          e[u] = 0;
+          if (i0 + u < cnt) e[u] = first ? (int32_t)(i0 + u) : ldc(&A[i0 + u]);
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          sv[u] = make_int2(0, 1);
+          if (i0 + u < cnt) sv[u] = ldc2(&P.sr[e[u]]);
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+          live[u] = sv[u].y == 0;
+          take[u] = false;
+          if (live[u]) {
+            mins = sv[u].x < mins ? sv[u].x : mins;
+            take[u] = sv[u].x <= kt - 2;
+            if (take[u]) {
+              stc_stamp(&P.sr[e[u]], stamp);
+              P.truss[e[u]] = kt;
+              const int du = P.rlen[P.eu[e[u]]], dv = P.rlen[P.ev[e[u]]];
               wsum += (unsigned long long)(du < dv ? du : dv);
             }
           }
         }
-        staged_append(LA, live, e, s_tmp);
-        staged_append(LQ, take, e, s_tmp);
+        staged_append_n<SU>(LA, live, e, s_tmp);
+        // the frontier stage holds two entries a thread per append
+#pragma unroll
+        for (int h = 0; h < SU; h += 2) {
+          const bool th[2] = {take[h], take[h + 1]};
+          const int32_t eh[2] = {e[h], e[h + 1]};
+          staged_append_n<2>(LQ, th, eh, s_tmp);
+        }
       }
       staged_flush(LA);
       staged_flush(LQ);
@@ -970,9 +1021,9 @@ __device__ __forceinline__ void peel_body(const PeelArgs& P) {
 // per thread, or two workgroups per compute unit (registers capped for eight
 // wavefronts per SIMD) with two entries per thread, which hides more latency
 // when walks are long.  All state lives in global memory between launches.
-__global__ void __launch_bounds__(kT) k_peel(PeelArgs P) { peel_body<4>(P); }
+__global__ void __launch_bounds__(kT) k_peel(PeelArgs P) { peel_body<4, 4>(P); }
 __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(8, 8))) k_peel_wide(PeelArgs P) {
-  peel_body<2>(P);
+  peel_body<2, 2>(P);
 }
 
 // One bit per edge, set when the edge is removed: the liveness test of the
@@ -991,6 +1042,7 @@ __global__ void __launch_bounds__(256) k_dead_bits(const int2* __restrict__ sr, 
 }
 
 // Stable in-place compaction of every row to its live entries (a wavefront a row).
+constexpr int kCompactUnroll = 4;
 __global__ void __launch_bounds__(256) k_compact(const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col,
                                                  int32_t* __restrict__ seid, int32_t* __restrict__ rlen, int32_t n,
                                                  const unsigned long long* __restrict__ dead, PeelCtl* c) {
@@ -1005,22 +1057,37 @@ __global__ void __launch_bounds__(256) k_compact(const int64_t* __restrict__ row
     const int64_t rb = row_ptr[v];
     const int len = rlen[v];
     int wpos = 0;
-    for (int c0 = 0; c0 < len; c0 += kWave) {
-      const int i = c0 + lane;
-      int32_t x = 0, ed = 0;
-      bool keep = false;
-      if (i < len) {
-        x = col[rb + i];
-        ed = seid[rb + i];
-        keep = ((dead[ed >> 6] >> (ed & 63)) & 1ULL) == 0;
+    // kCompactUnroll chunks of kWave entries are read before any is written
+    // back, so their loads overlap; entries only move to lower positions, so
+    // the writes never reach an entry that has not been read
+    for (int c0 = 0; c0 < len; c0 += kCompactUnroll * kWave) {
+      int32_t x[kCompactUnroll], ed[kCompactUnroll];
+      bool keep[kCompactUnroll];
+#pragma unroll
+      for (int u = 0; u < kCompactUnroll; ++u) {
+        const int i = c0 + u * kWave + lane;
+        x[u] = 0;
+        ed[u] = 0;
+        if (i < len) {
+          x[u] = col[rb + i];
+          ed[u] = seid[rb + i];
+        }
       }
-      const uint64_t km = ballot(keep);
-      if (keep) {
-        const int64_t dst = rb + wpos + rank_below(km);
-        col[dst] = x;
-        seid[dst] = ed;
+#pragma unroll
+      for (int u = 0; u < kCompactUnroll; ++u) {
+        const int i = c0 + u * kWave + lane;
+        keep[u] = i < len && ((dead[ed[u] >> 6] >> (ed[u] & 63)) & 1ULL) == 0;
       }
-      wpos += __popcll(km);
+#pragma unroll
+      for (int u = 0; u < kCompactUnroll; ++u) {
+        const uint64_t km = ballot(keep[u]);
+        if (keep[u]) {
+          const int64_t dst = rb + wpos + rank_below(km);
+          col[dst] = x[u];
+          seid[dst] = ed[u];
+        }
+        wpos += __popcll(km);
+      }
     }
     if (lane == 0) rlen[v] = wpos;
   }
