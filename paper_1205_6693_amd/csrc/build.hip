@@ -2,6 +2,8 @@
 // edge ids, the symmetric CSR with edge ids, and the (degree, id) orientation
 // used for triangle listing (the in-memory triangle counting that Algorithm 2,
 // starts from; the smaller-degree rule of its triangle walk and Theorem 1).
+#include <utility>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -33,6 +35,53 @@ __global__ void k_fill(T* p, int64_t n, T v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
+
+// ---- row hash tables (the membership test of Algorithm 2) -----------------------------------
+
+// slots of v's table: the power of two >= 2 deg(v) (0 for an isolated vertex)
+__global__ void k_rtab_sizes(const int64_t* __restrict__ row_ptr, int32_t n, int32_t* __restrict__ tsz) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t d = row_ptr[v + 1] - row_ptr[v];
+  int64_t sz = 0;
+  if (d > 0) {
+    sz = 2;
+    while (sz < 2 * d) sz <<= 1;
+  }
+  tsz[v] = (int32_t)sz;
+}
+
+__global__ void k_rtab_clear(int2* __restrict__ rtab, const int64_t* __restrict__ rtoff, int32_t n, int64_t cap) {
+  const int64_t total = rtoff[n];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total && i < cap;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rtab[i] = make_int2(-1, 0);
+}
+
+__device__ __forceinline__ void rtab_put(int2* __restrict__ rtab, const int64_t* __restrict__ rtoff, int32_t v,
+                                         int32_t w, int32_t e) {
+  const int64_t off = rtoff[v];
+  const int lg = row_table_lg(rtoff[v + 1] - off);
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = row_slot(w, lg);
+  // neighbours are distinct and the table is at most half full: a free slot is found
+  while (atomicCAS(&rtab[off + h].x, -1, w) != -1) h = (h + 1) & mask;
+  rtab[off + h].y = e;
+}
+
+// a thread per edge (u, v) inserts v into u's table and u into v's table (CSR
+// input used as it is; the sorted builds insert while placing the row entries)
+__global__ void k_rtab_insert(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
+                              const int64_t* __restrict__ rtoff, int2* __restrict__ rtab) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int32_t u = eu[e], v = ev[e];
+  rtab_put(rtab, rtoff, u, v, (int32_t)e);
+  rtab_put(rtab, rtoff, v, u, (int32_t)e);
+}
+
+// capacity bound: 2^ceil(log2(2d)) < 4d for d >= 1, so all tables fit in 8m slots
+inline int64_t rtab_capacity(int64_t m) { return 8 * m + 2; }
 
 // ---- edge-list input ----------------------------------------------------------------
 
@@ -82,10 +131,12 @@ __global__ void k_row_bounds(const int32_t* __restrict__ eu, const int32_t* __re
 }
 
 // upper entry of canonical edge e = (u, v): the tail of u's row, after its
-// lower entries (row_ptr[u+1] = uppre[u+1] + lowpre[u+1])
+// lower entries (row_ptr[u+1] = uppre[u+1] + lowpre[u+1]); and v into u's row table
+// (the threads of a block share u, so their inserts land in one table)
 __global__ void k_sym_upper(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
                             const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ lowpre,
-                            int32_t* __restrict__ col, int32_t* __restrict__ seid, int32_t* __restrict__ kf) {
+                            int32_t* __restrict__ col, int32_t* __restrict__ seid, int32_t* __restrict__ kf,
+                            const int64_t* __restrict__ rtoff, int2* __restrict__ rtab) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= m) return;
   int32_t u = eu[e], v = ev[e];
@@ -93,6 +144,7 @@ __global__ void k_sym_upper(const int32_t* __restrict__ eu, const int32_t* __res
   col[pos] = v;
   seid[pos] = (int32_t)e;
   kf[pos] = vertex_before(deg_of(row_ptr, u), u, deg_of(row_ptr, v), v) ? 1 : 0;
+  rtab_put(rtab, rtoff, u, v, (int32_t)e);
 }
 
 __global__ void k_copy_ev(const int32_t* __restrict__ ev, int64_t m, uint32_t* __restrict__ tkey,
@@ -104,11 +156,13 @@ __global__ void k_copy_ev(const int32_t* __restrict__ ev, int64_t m, uint32_t* _
 }
 
 // lower entry of edge tval[t] = (u, v) with v = tkey[t]: the head of v's row,
-// in canonical order (row_ptr[v] = uppre[v] + lowpre[v])
+// in canonical order (row_ptr[v] = uppre[v] + lowpre[v]); and u into v's row
+// table (threads sorted by v, so again one table per run of threads)
 __global__ void k_sym_lower(const uint32_t* __restrict__ tkey, const int32_t* __restrict__ tval, int64_t m,
                             const int64_t* __restrict__ row_ptr, const int64_t* __restrict__ uppre,
                             const int32_t* __restrict__ eu, int32_t* __restrict__ col,
-                            int32_t* __restrict__ seid, int32_t* __restrict__ kf) {
+                            int32_t* __restrict__ seid, int32_t* __restrict__ kf,
+                            const int64_t* __restrict__ rtoff, int2* __restrict__ rtab) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= m) return;
   int32_t e = tval[t];
@@ -118,6 +172,7 @@ __global__ void k_sym_lower(const uint32_t* __restrict__ tkey, const int32_t* __
   col[pos] = u;
   seid[pos] = e;
   kf[pos] = vertex_before(deg_of(row_ptr, v), v, deg_of(row_ptr, u), u) ? 1 : 0;
+  rtab_put(rtab, rtoff, v, u, e);
 }
 
 // ---- locality relabelling ------------------------------------------------------------
@@ -282,53 +337,6 @@ __global__ void k_ocsr(const int32_t* __restrict__ col, const int32_t* __restric
   }
 }
 
-// ---- row hash tables (the membership test of Algorithm 2) -----------------------------------
-
-// slots of v's table: the power of two >= 2 deg(v) (0 for an isolated vertex)
-__global__ void k_rtab_sizes(const int64_t* __restrict__ row_ptr, int32_t n, int32_t* __restrict__ tsz) {
-  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int64_t d = row_ptr[v + 1] - row_ptr[v];
-  int64_t sz = 0;
-  if (d > 0) {
-    sz = 2;
-    while (sz < 2 * d) sz <<= 1;
-  }
-  tsz[v] = (int32_t)sz;
-}
-
-__global__ void k_rtab_clear(int2* __restrict__ rtab, const int64_t* __restrict__ rtoff, int32_t n, int64_t cap) {
-  const int64_t total = rtoff[n];
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total && i < cap;
-       i += (int64_t)gridDim.x * blockDim.x)
-    rtab[i] = make_int2(-1, 0);
-}
-
-// a thread per edge (u, v) inserts v into u's table and u into v's table
-// (consecutive edges share u, so the first inserts of a warp land together)
-__device__ __forceinline__ void rtab_put(int2* __restrict__ rtab, const int64_t* __restrict__ rtoff, int32_t v,
-                                         int32_t w, int32_t e) {
-  const int64_t off = rtoff[v];
-  const int lg = row_table_lg(rtoff[v + 1] - off);
-  const uint32_t mask = (1u << lg) - 1u;
-  uint32_t h = row_slot(w, lg);
-  // neighbours are distinct and the table is at most half full: a free slot is found
-  while (atomicCAS(&rtab[off + h].x, -1, w) != -1) h = (h + 1) & mask;
-  rtab[off + h].y = e;
-}
-
-__global__ void k_rtab_insert(const int32_t* __restrict__ eu, const int32_t* __restrict__ ev, int64_t m,
-                              const int64_t* __restrict__ rtoff, int2* __restrict__ rtab) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  const int32_t u = eu[e], v = ev[e];
-  rtab_put(rtab, rtoff, u, v, (int32_t)e);
-  rtab_put(rtab, rtoff, v, u, (int32_t)e);
-}
-
-// capacity bound: 2^ceil(log2(2d)) < 4d for d >= 1, so all tables fit in 8m slots
-inline int64_t rtab_capacity(int64_t m) { return 8 * m + 2; }
-
 int read_err(const int* d_err, hipStream_t s) {
   int h = kNoErr;
   TRUSS_HIP(hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -422,14 +430,26 @@ void carve(const truss_graph* g, bool relabel, Arena& a, Layout& L) {
 void degree_ranks(const int64_t* row_ptr, const int32_t* deg, int32_t n, int vb, Layout& L, hipStream_t s) {
   hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, row_ptr, deg, n, vb, L.vkey,
                      L.vval);
-  radix_sort_u64(L.vkey, L.vval, L.vkey_alt, L.vval_alt, n, 2 * vb, L.vtmp, s);
-  hipLaunchKernelGGL(k_ranks, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, L.vval, n, L.rank);
+  const bool alt = radix_sort_u64(L.vkey, L.vval, L.vkey_alt, L.vval_alt, n, 2 * vb, L.vtmp, s);
+  hipLaunchKernelGGL(k_ranks, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, alt ? L.vval_alt : L.vval, n, L.rank);
 }
 
-// symmetric CSR, canonical edges and perm from the unsorted canonical keys in
-// L.key / L.val (val: the caller's index of each edge)
+// sizes, offsets and cleared slots of the row tables for the rows at row_ptr
+void table_layout(const int64_t* row_ptr, int32_t n, int64_t m, Layout& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_rtab_sizes, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, row_ptr, n, L.tsz);
+  scan_exclusive_i32_to_i64(L.tsz, L.rtoff, n, L.stmp, s);
+  const int64_t cap = rtab_capacity(m);
+  hipLaunchKernelGGL(k_rtab_clear, dim3(grid_for(cap) < 65536 ? grid_for(cap) : 65536), dim3(kT), 0, s, L.rtab,
+                     L.rtoff, n, cap);
+}
+
+// symmetric CSR, canonical edges, perm and the row tables from the unsorted
+// canonical keys in L.key / L.val (val: the caller's index of each edge)
 int rows_from_keys(int32_t n, int64_t m, int vb, Layout& L, int* d_err, hipStream_t s) {
-  radix_sort_u64(L.key, L.val, L.key_alt, L.val_alt, m, 2 * vb, L.rtmp, s);
+  if (radix_sort_u64(L.key, L.val, L.key_alt, L.val_alt, m, 2 * vb, L.rtmp, s)) {
+    std::swap(L.key, L.key_alt);
+    std::swap(L.val, L.val_alt);
+  }
   hipLaunchKernelGGL(k_edges_from_keys, dim3(grid_for(m)), dim3(kT), 0, s, L.key, L.val, m, vb, L.eu, L.ev, L.perm,
                      d_err);
   const int rc = read_err(d_err, s);
@@ -438,13 +458,17 @@ int rows_from_keys(int32_t n, int64_t m, int vb, Layout& L, int* d_err, hipStrea
   uint32_t* tkey = reinterpret_cast<uint32_t*>(L.key);
   uint32_t* tkey_alt = reinterpret_cast<uint32_t*>(L.key_alt);
   hipLaunchKernelGGL(k_copy_ev, dim3(grid_for(m)), dim3(kT), 0, s, L.ev, m, tkey, L.val);
-  radix_sort_u32(tkey, L.val, tkey_alt, L.val_alt, m, vb, L.rtmp, s);
+  if (radix_sort_u32(tkey, L.val, tkey_alt, L.val_alt, m, vb, L.rtmp, s)) {
+    std::swap(tkey, tkey_alt);
+    std::swap(L.val, L.val_alt);
+  }
   hipLaunchKernelGGL(k_row_bounds, dim3(grid_for((int64_t)n + 1)), dim3(kT), 0, s, L.eu,
                      reinterpret_cast<const int32_t*>(tkey), m, n, L.uppre, L.lowpre, L.row_ptr);
+  table_layout(L.row_ptr, n, m, L, s);
   hipLaunchKernelGGL(k_sym_upper, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.row_ptr, L.lowpre, L.col,
-                     L.seid, L.kf);
+                     L.seid, L.kf, L.rtoff, L.rtab);
   hipLaunchKernelGGL(k_sym_lower, dim3(grid_for(m)), dim3(kT), 0, s, tkey, L.val, m, L.row_ptr, L.uppre, L.eu,
-                     L.col, L.seid, L.kf);
+                     L.col, L.seid, L.kf, L.rtoff, L.rtab);
   return TRUSS_OK;
 }
 
@@ -532,14 +556,12 @@ int build_graph(const truss_graph* g, Arena& a, DevGraph& dg, int* d_err, hipStr
   dg.orow = L.orow;
   dg.ocol = L.ocol;
   dg.oeid = L.oeid;
-  // row hash tables for the membership tests of peeling
-  hipLaunchKernelGGL(k_rtab_sizes, dim3(grid_for(n > 0 ? n : 1)), dim3(kT), 0, s, dg.row_ptr, n, L.tsz);
-  scan_exclusive_i32_to_i64(L.tsz, L.rtoff, n, L.stmp, s);
-  const int64_t cap = rtab_capacity(m);
-  hipLaunchKernelGGL(k_rtab_clear, dim3(grid_for(cap) < 65536 ? grid_for(cap) : 65536), dim3(kT), 0, s, L.rtab,
-                     L.rtoff, n, cap);
-  if (m > 0)
-    hipLaunchKernelGGL(k_rtab_insert, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.rtoff, L.rtab);
+  // row hash tables for the membership tests of peeling (the sorted builds
+  // filled them while placing the row entries)
+  if (dg.perm == nullptr) {
+    table_layout(dg.row_ptr, n, m, L, s);
+    if (m > 0) hipLaunchKernelGGL(k_rtab_insert, dim3(grid_for(m)), dim3(kT), 0, s, L.eu, L.ev, m, L.rtoff, L.rtab);
+  }
   TRUSS_HIP(hipGetLastError());
   dg.rtab = L.rtab;
   dg.rtoff = L.rtoff;

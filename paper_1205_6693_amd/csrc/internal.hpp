@@ -41,12 +41,14 @@ void scan_exclusive_i32_to_i32(const int32_t* in, int32_t* out, int64_t count, i
                                hipStream_t s);
 
 // ---- radix sort (LSD, 8-bit digits, stable) -------------------------------------
-// Sorts (keys, vals) of length n by the low `bits` bits of the keys.  Uses the
-// *_alt buffers as ping-pong storage; the result ends in keys/vals.
+// Sorts (keys, vals) of length n by the low `bits` bits of the keys, passing
+// back and forth between the two buffer pairs: returns true when the sorted
+// result ended in keys_alt/vals_alt (an odd number of passes), false when it
+// is in keys/vals.
 size_t radix_tmp_elems(int64_t n);
-void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
+bool radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt,
                     int64_t n, int bits, int32_t* tmp, hipStream_t s);
-void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
+bool radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt,
                     int64_t n, int bits, int32_t* tmp, hipStream_t s);
 
 // ---- the resident graph ---------------------------------------------------------

@@ -198,9 +198,9 @@ __global__ void __launch_bounds__(kRadixThreads) k_rs_scatter(const K* __restric
 }
 
 template <typename K>
-void radix_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t n, int bits,
+bool radix_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t n, int bits,
                 int32_t* tmp, hipStream_t s) {
-  if (n <= 1 || bits <= 0) return;
+  if (n <= 1 || bits <= 0) return false;
   const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
   int32_t* counts = tmp;
   int32_t* offs = counts + 256 * ntiles;
@@ -217,10 +217,7 @@ void radix_impl(K* keys, int32_t* vals, K* keys_alt, int32_t* vals_alt, int64_t 
     K* tk = kin; kin = kout; kout = tk;
     int32_t* tv = vin; vin = vout; vout = tv;
   }
-  if (kin != keys) {
-    hipMemcpyAsync(keys, kin, sizeof(K) * (size_t)n, hipMemcpyDeviceToDevice, s);
-    hipMemcpyAsync(vals, vin, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s);
-  }
+  return kin != keys;
 }
 
 }  // namespace
@@ -240,14 +237,14 @@ size_t radix_tmp_elems(int64_t n) {
   return (size_t)(2 * 256 * ntiles + 1) + scan_tmp_elems(256 * ntiles);
 }
 
-void radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
+bool radix_sort_u64(uint64_t* keys, int32_t* vals, uint64_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
                     int32_t* tmp, hipStream_t s) {
-  radix_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s);
+  return radix_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s);
 }
 
-void radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
+bool radix_sort_u32(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, int64_t n, int bits,
                     int32_t* tmp, hipStream_t s) {
-  radix_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s);
+  return radix_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s);
 }
 
 }  // namespace truss
