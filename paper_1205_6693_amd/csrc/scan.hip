@@ -150,6 +150,13 @@ __global__ void __launch_bounds__(kRadixThreads) k_rs_hist(const K* __restrict__
   counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
 }
 
+// Stable scatter of one tile.  Wavefront w owns the tile's elements
+// [w * kWave * kRadixItems, (w + 1) * kWave * kRadixItems), item j of lane l
+// being element w * kWave * kRadixItems + j * kWave + l, so (wavefront, item,
+// lane) is the input order.  Each wavefront ranks its items one after another
+// by wavefront match (eight ballots) against its own per-digit counters, with
+// no workgroup barrier between items; one barrier later the per-digit
+// prefix over the wavefronts places every element.
 template <typename K>
 __global__ void __launch_bounds__(kRadixThreads) k_rs_scatter(const K* __restrict__ keys, const int32_t* __restrict__ vals,
                                                                int64_t n, int shift, const int32_t* __restrict__ offs,
@@ -157,17 +164,24 @@ __global__ void __launch_bounds__(kRadixThreads) k_rs_scatter(const K* __restric
                                                                int32_t* __restrict__ vals_out) {
   __shared__ int run[256];
   __shared__ int wcnt[kRadixWaves][256];
+  const int w = threadIdx.x / kWave, lane = lane_id();
   run[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
-  for (int w = 0; w < kRadixWaves; ++w) wcnt[w][threadIdx.x] = 0;
+  for (int q = 0; q < kRadixWaves; ++q) wcnt[q][threadIdx.x] = 0;
   __syncthreads();
-  const int w = threadIdx.x / kWave;
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)w * kWave * kRadixItems;
+  K k[kRadixItems];
+  int32_t val[kRadixItems];
+  int rk[kRadixItems];  // position among the wavefront's elements of the same digit
+#pragma unroll
   for (int j = 0; j < kRadixItems; ++j) {
-    const int64_t i = base + j * kRadixThreads + threadIdx.x;
-    const bool valid = i < n;
-    K k = valid ? keys[i] : (K)0;
-    int32_t val = valid ? vals[i] : 0;
-    const int d = (int)((k >> shift) & 255);
+    const int64_t i = base + j * kWave + lane;
+    k[j] = i < n ? keys[i] : (K)0;
+    val[j] = i < n ? vals[i] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < kRadixItems; ++j) {
+    const bool valid = base + j * kWave + lane < n;
+    const int d = (int)((k[j] >> shift) & 255);
     uint64_t peers = ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -175,25 +189,31 @@ __global__ void __launch_bounds__(kRadixThreads) k_rs_scatter(const K* __restric
       const uint64_t bb = ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const int rank = rank_below(peers);
-    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-    __syncthreads();
-    if (valid) {
-      int pos = run[d] + rank;
-      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
-      keys_out[pos] = k;
-      vals_out[pos] = val;
+    rk[j] = 0;
+    if (valid) rk[j] = wcnt[w][d] + rank_below(peers);
+    wave_sync();
+    if (valid && rank_below(peers) == 0) wcnt[w][d] += __popcll(peers);
+    wave_sync();
+  }
+  __syncthreads();
+  // thread t: digit t's start for each wavefront
+  {
+    int acc = run[threadIdx.x];
+    for (int q = 0; q < kRadixWaves; ++q) {
+      const int c = wcnt[q][threadIdx.x];
+      wcnt[q][threadIdx.x] = acc;
+      acc += c;
     }
-    __syncthreads();
-    {
-      int tot = 0;
-      for (int q = 0; q < kRadixWaves; ++q) {
-        tot += wcnt[q][threadIdx.x];
-        wcnt[q][threadIdx.x] = 0;
-      }
-      run[threadIdx.x] += tot;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRadixItems; ++j) {
+    if (base + j * kWave + lane < n) {
+      const int d = (int)((k[j] >> shift) & 255);
+      const int pos = wcnt[w][d] + rk[j];
+      keys_out[pos] = k[j];
+      vals_out[pos] = val[j];
     }
-    __syncthreads();
   }
 }
 
