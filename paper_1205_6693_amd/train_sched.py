@@ -1,7 +1,8 @@
 """Trains the learned scheduler's model file (sched_model.json beside this file).
 
-Training graphs are seeded synthetic graphs (seeds >= 1000) smaller than the
-largest workloads: R-MAT (scales 14-22, edge factors 8-128), Chung-Lu
+Training graphs are seeded synthetic graphs (seeds >= 1000): R-MAT (scales
+14-23, edge factors 8-128; scale 23 with edge factor 20 is above 2^27 edges,
+so its levels are timed on the wide peeling shape), Chung-Lu
 power-law graphs with planted cliques (up to 2^21 vertices, cliques up to 4600
 vertices) and Erdos-Renyi graphs.  For each, exhaustive timing (sched.exhaustive) records the time of
 every action at every decision; both model parts are then fitted on the GPU by
@@ -46,6 +47,8 @@ TRAIN = [
     # larger graphs (still below the R-MAT 24 and Chung-Lu 4M workloads)
     ("rmat", 20, 16, 1030), ("rmat", 21, 16, 1031), ("rmat", 22, 16, 1032), ("rmat", 21, 8, 1033),
     ("cl", 1 << 21, 30, 64, 50, 500, 1034),
+    # above 2^27 edges, where the peeling kernel takes its wide shape
+    ("rmat", 23, 20, 1035),
 ]
 HELDOUT = [("rmat", 17, 16, 2000), ("cl", 1 << 19, 30, 48, 50, 400, 2001), ("rmat", 19, 12, 2002)]
 
